@@ -1,0 +1,170 @@
+/*
+ * mbd.h - C ABI of the MI355X SPME stochastic-Lanczos many-body dispersion library.
+ *
+ * What it computes (arXiv 2307.02278):
+ *   E_MBD = 1/2 Tr sqrt(C) - 3/2 sum_i omega_i                     (eq. plasmonic2)
+ * with the periodic MBD coupling matrix (eq. ham, eqs. vmbd/ccd/gvec)
+ *   C = Omega + Diag(g) T^pbc Diag(g),  Omega = diag(omega_i^2 I_3),  g_i = omega_i sqrt(alpha_i),
+ * estimated by stochastic Lanczos quadrature: Hutchinson trace over R normalized
+ * Rademacher probes (eqs. hutch, dds) and an m-point Gauss quadrature from the
+ * Lanczos tridiagonal of each probe (eqs. sl3, sl4, tridiag1, tridiag2; Algorithm 1).
+ * Every Lanczos step applies C through generalized dipoles d = g * y and their
+ * Ewald field E* = E_dir + E_rec + E_self (eqs. ewalddip, lk3, recurs2; Algorithm 2):
+ *   - E_dir: erfc-screened dipole field plus the damping correction -(1 - f) T,
+ *            summed over all periodic images within a cutoff (eq. fld_ewald);
+ *   - E_rec: smooth particle-mesh Ewald: B-spline spreading of the dipoles,
+ *            3D FFT, influence-function convolution, inverse FFT, derivative
+ *            gather (eqs. scaledfractional, spme, dipolarr);
+ *   - E_self = -(4 tau^3 / (3 sqrt(pi))) d  (eq. fld_ewald1, field coefficient).
+ * The damping f is the Fermi function 1 / (1 + exp(-d (r / S_ij - 1))),
+ * S_ij = beta (R_vdW,i + R_vdW,j) (the paper defers its explicit form to its
+ * stochastic-MBD reference; this is the rsSCS form with range beta).
+ *
+ * Units: atomic units everywhere (bohr, bohr^3, Hartree, Hartree/bohr).
+ * Field sign: "energy convention", E = T d with dipole-dipole energy d_i^T T_ij d_j.
+ *
+ * Conventions for every entry point:
+ *   - Array arguments marked "device" are device pointers on the plan's GPU and
+ *     are owned by the caller. The plan owns its workspace (allocated in
+ *     mbd_plan_create); mbd_execute and mbd_matvec allocate nothing.
+ *   - All work is enqueued on the stream given at plan creation (a hipStream_t,
+ *     passed as void*; NULL = the default stream). Calls return once the work is
+ *     enqueued unless stated otherwise. A plan is bound to one stream and one
+ *     device and is not thread-safe.
+ *   - Every call returns an mbd_status; no exception crosses the ABI. Argument
+ *     checks happen on the host before any device work and leave the plan
+ *     unchanged. mbd_last_error() gives a thread-local message for the last
+ *     failure.
+ *   - Vectors at the boundary use the caller's atom order, layout [nrhs][n][3],
+ *     float64. Internal layouts (atoms sorted by cell, RHS innermost) never leak.
+ */
+#ifndef MBD_H
+#define MBD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mbd_plan_s* mbd_plan;
+typedef int32_t mbd_status;
+
+enum {
+  MBD_OK = 0,
+  MBD_E_ARG = -1,         /* invalid argument (sizes, parameters, NULL pointers)          */
+  MBD_E_CELL = -2,        /* cell is not orthorhombic (only diagonal cells are supported)  */
+  MBD_E_GRID = -3,        /* grid size unsupported (see mbd_grid_supported) or < 2p        */
+  MBD_E_NOT_POSDEF = -4,  /* a Ritz value theta_k <= 0: C is not positive definite         */
+  MBD_E_NONFINITE = -5,   /* NaN/Inf met in a field, a Lanczos scalar or the energy        */
+  MBD_E_NODEVICE = -6,    /* no usable GPU                                                 */
+  MBD_E_HIP = -7,         /* a HIP runtime call failed                                     */
+  MBD_E_OOM = -8,         /* device allocation failed                                      */
+  MBD_E_STATE = -9        /* call out of order (e.g. tridiagonal requested before execute) */
+};
+
+enum { MBD_PREC_FP64 = 0, MBD_PREC_MIXED = 1 /* FP32 SPME + pair kernel, FP64 Lanczos */ };
+enum { MBD_REORTH_NONE = 0, MBD_REORTH_LOCAL = 1, MBD_REORTH_FULL = 2 };
+enum { MBD_C_DIAG = 1, MBD_C_DIR = 2, MBD_C_REC = 4, MBD_C_SELF = 8, MBD_C_ALL = 15 };
+
+/* One periodic system. Positions may lie in any periodic image. */
+typedef struct {
+  int32_t n_atoms;      /* N >= 1                                                      */
+  const double* pos;    /* device [N][3], bohr                                          */
+  double cell[9];       /* host copy, rows a1, a2, a3 in bohr; must be diagonal         */
+  const double* alpha;  /* device [N], static polarizability alpha_i(0) > 0, bohr^3     */
+  const double* omega;  /* device [N], characteristic frequency omega_i > 0, Hartree    */
+  const double* r_vdw;  /* device [N], van der Waals radius > 0, bohr                   */
+} mbd_system;
+
+typedef struct {
+  double damp_beta;     /* range parameter beta of the Fermi damping (> 0), e.g. 0.83   */
+  double damp_d;        /* steepness d of the Fermi damping (> 0), e.g. 6               */
+  double ewald_tau;     /* Ewald splitting tau in 1/bohr; <= 0: derived from real_cutoff
+                           by erfc(tau r_c) / r_c = 1e-8 with r_c in Angstrom           */
+  double real_cutoff;   /* erfc cutoff r_c in bohr (> 0)                               */
+  double damp_tol;      /* pair kernel also runs to where 1 - f = damp_tol; 0 => 1e-7;
+                           < 0 => only real_cutoff is used                              */
+  int32_t grid[3];      /* SPME grid K1..K3; 0 => smallest even 2^a 3^b >= 1.4 / A     */
+  int32_t spline_order; /* B-spline order p (support of p points): even, 4..8; 0 => 6   */
+  int32_t n_probes;     /* R >= 1 Rademacher probes per system                          */
+  int32_t n_steps;      /* m >= 1 Lanczos steps (matvecs, size of the tridiagonal)      */
+  int32_t block;        /* probes in flight as one block of right-hand sides; 0 => R   */
+  uint64_t seed;        /* probe seed (SplitMix64 counter generator, see below)        */
+  int32_t precision;    /* MBD_PREC_FP64 or MBD_PREC_MIXED                              */
+  int32_t reorth;       /* MBD_REORTH_NONE / LOCAL / FULL                               */
+  int32_t want_forces;  /* reserved; must be 0 in this version                          */
+  int32_t deterministic;/* reserved; results are run-to-run reproducible up to float
+                           atomics in the spread kernel                                 */
+} mbd_params;
+
+/* Values derived on the host for one system of a plan. */
+typedef struct {
+  double tau;           /* 1/bohr                                                      */
+  double r_pair;        /* direct-space cutoff actually used, bohr                      */
+  int32_t grid[3];
+  int32_t spline_order;
+  int32_t cells[3];     /* cell-list cells per axis                                    */
+  int32_t block;        /* right-hand sides per block                                  */
+  size_t workspace_bytes;
+} mbd_info;
+
+/* Probe definition (eq. dds): entry (l, i, a) of system s is +-1/sqrt(3N), the sign
+ * taken from bit 63 of SplitMix64 output number (l*3N + 3i + a) of the stream seeded
+ * with z_s, where z_s is output number s of the stream seeded with `seed`. Output n of
+ * a stream seeded with x is mix(x + (n+1) * 0x9E3779B97F4A7C15) (Steele, Lea, Flood 2014).
+ * i is the atom's index in the caller's order. */
+
+/* Create a plan for n_sys systems with shared parameters. Validates every argument,
+ * derives tau / cutoffs / grids, allocates the whole workspace, sorts atoms into cells
+ * and builds B-spline tables and the influence function (device setup, Algorithm 1
+ * lines on grid allocation and neighbour lists). `stream` is a hipStream_t or NULL.
+ * Returns MBD_E_ARG / MBD_E_CELL / MBD_E_GRID without touching the device on bad input. */
+mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_sys,
+                           const mbd_params* prm, void* stream);
+
+mbd_status mbd_plan_info(mbd_plan plan, int32_t sys, mbd_info* info);
+
+/* Re-run the position-dependent setup with new positions (device [N][3]) for one system. */
+mbd_status mbd_set_positions(mbd_plan plan, int32_t sys, const double* pos);
+
+/* Run Algorithm 1 for every system: R probes in blocks of `block` RHS, m Lanczos steps
+ * each, Gauss quadrature per probe, then E = 1/2 (3N/R) sum_l Q_l - 3/2 sum omega.
+ * energy: device [n_sys] float64. forces must be NULL in this version. */
+mbd_status mbd_execute(mbd_plan plan, double* energy, double* forces);
+
+/* Synchronize the plan's stream and return the first device-detected error
+ * (MBD_E_NOT_POSDEF, MBD_E_NONFINITE) since the last execute, else MBD_OK. */
+mbd_status mbd_check(mbd_plan plan);
+
+/* out = C_sel v for nrhs vectors (test and diagnostic hook). v, out: device
+ * [nrhs][N][3] float64 in the caller's atom order; 1 <= nrhs <= block.
+ * components selects the parts of C: MBD_C_DIAG (Omega v), MBD_C_DIR
+ * (g * E_dir(g v)), MBD_C_REC (g * E_rec(g v)), MBD_C_SELF (g * E_self(g v)). */
+mbd_status mbd_matvec(mbd_plan plan, int32_t sys, const double* v, double* out,
+                      int32_t nrhs, uint32_t components);
+
+/* Lanczos tridiagonals of the last execute (synchronizes). Host arrays:
+ * a [R][m] diagonal, b [R][m] with b[l][k] = b_{k+1} (off-diagonal between k and k+1,
+ * b[l][m-1] unused), m_eff [R] steps done before a breakdown. */
+mbd_status mbd_get_tridiagonal(mbd_plan plan, int32_t sys, double* a, double* b,
+                               int32_t* m_eff);
+
+/* Per-probe quadrature values Q_l = sum_k U_1k^2 sqrt(theta_k) of the last execute
+ * (synchronizes). q: host [R]. */
+mbd_status mbd_get_quadrature(mbd_plan plan, int32_t sys, double* q);
+
+mbd_status mbd_plan_destroy(mbd_plan plan);
+
+/* 1 if an FFT of length k is compiled in (even 2^a 3^b 5^c in [8, 128]), else 0. */
+int32_t mbd_grid_supported(int32_t k);
+
+const char* mbd_status_string(mbd_status s);
+const char* mbd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MBD_H */

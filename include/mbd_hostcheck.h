@@ -1,0 +1,40 @@
+/*
+ * mbd_hostcheck.h - the scalar mathematics of the GPU kernels, compiled for the CPU.
+ *
+ * For CPU-side checks only (libmbd_hostcheck.so): these functions run the exact
+ * host+device source the kernels use, on the host, so that it can be compared
+ * with an independent reference without a GPU. All pointers are host memory
+ * owned by the caller. No function here touches a device.
+ */
+#ifndef MBD_HOSTCHECK_H
+#define MBD_HOSTCHECK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Output number n of the SplitMix64 stream seeded with `seed` (probe signs, eq. dds). */
+uint64_t mbdh_splitmix(uint64_t seed, uint64_t n);
+
+/* B-spline weights th[t] = M_p(w + t), dth[t] = M_p'(w + t), t = 0..p-1, p in {4,6,8},
+ * w in [0, 1) (interpolation of eq. scaledfractional / spme). Returns 0, or -1 for bad p. */
+int32_t mbdh_bspline(int32_t p, double w, double* th, double* dth);
+
+/* Direct-space kernel T_dir = A I - B r r^T at distance^2 r2 (eq. fld_ewald with the
+ * damping correction), in double (prec 0) or single (prec 1) precision. */
+void mbdh_direct_kernel(int32_t prec, double r2, double tau, double inv_s, double damp_d,
+                        double* A, double* B);
+
+/* Gauss quadrature sum_k U_1k^2 sqrt(theta_k) of the symmetric tridiagonal with diagonal
+ * a[0..n-1] and off-diagonal b[0..n-2] (eqs. sl3, tridiag2). Inputs are not modified;
+ * theta_min receives the smallest eigenvalue; returns 1 on convergence, else 0. */
+int32_t mbdh_tridiag_quadrature(const double* a, const double* b, int32_t n, double* q,
+                                double* theta_min);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

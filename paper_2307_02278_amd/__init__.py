@@ -1,0 +1,11 @@
+"""MI355X (gfx950) SPME stochastic-Lanczos MBD energy: HIP kernels behind a C ABI.
+
+The compute path is libmbd.so (built by paper_2307_02278_amd.build). Importing
+this package does not load it; the first call into the binding does, and it
+raises ImportError when the library is not built. There is no CPU fallback.
+"""
+from ._lib import (  # noqa: F401
+    C_ALL, C_DIAG, C_DIR, C_REC, C_SELF, PREC_FP64, PREC_MIXED, REORTH_FULL, REORTH_LOCAL,
+    REORTH_NONE, MbdError,
+)
+from .api import DeviceSystem, Params, Plan, energy  # noqa: F401

@@ -1,0 +1,153 @@
+"""Python entry points over the C ABI. PyTorch supplies device memory and the
+current HIP stream; every step of the computation runs in libmbd's kernels."""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+
+@dataclass
+class Params:
+    damp_beta: float = 0.83
+    damp_d: float = 6.0
+    ewald_tau: float = 0.0          # 1/bohr; 0 => from real_cutoff
+    real_cutoff: float = 9.0 / 0.529177210903
+    damp_tol: float = 0.0           # 0 => 1e-7
+    grid: Sequence[int] = (0, 0, 0)
+    spline_order: int = 6
+    n_probes: int = 8
+    n_steps: int = 30
+    block: int = 0
+    seed: int = 12345
+    precision: int = L.PREC_FP64
+    reorth: int = L.REORTH_NONE
+
+    def to_c(self) -> L.MbdParams:
+        p = L.MbdParams()
+        p.damp_beta = self.damp_beta
+        p.damp_d = self.damp_d
+        p.ewald_tau = self.ewald_tau
+        p.real_cutoff = self.real_cutoff
+        p.damp_tol = self.damp_tol
+        g = list(self.grid) + [0] * (3 - len(self.grid))
+        for a in range(3):
+            p.grid[a] = int(g[a])
+        p.spline_order = self.spline_order
+        p.n_probes = self.n_probes
+        p.n_steps = self.n_steps
+        p.block = self.block
+        p.seed = self.seed
+        p.precision = self.precision
+        p.reorth = self.reorth
+        p.want_forces = 0
+        p.deterministic = 0
+        return p
+
+
+class DeviceSystem:
+    """Device-resident copy of one periodic system (float64, atomic units)."""
+
+    def __init__(self, pos, cell, alpha, omega, rvdw, device="cuda"):
+        f = lambda x: torch.as_tensor(x, dtype=torch.float64).to(device).contiguous()
+        self.pos = f(pos).reshape(-1, 3).contiguous()
+        self.alpha = f(alpha)
+        self.omega = f(omega)
+        self.rvdw = f(rvdw)
+        self.cell = [float(x) for x in torch.as_tensor(cell, dtype=torch.float64).reshape(9)]
+        self.n = int(self.pos.shape[0])
+
+    def to_c(self) -> L.MbdSystem:
+        s = L.MbdSystem()
+        s.n_atoms = self.n
+        s.pos = self.pos.data_ptr()
+        for i in range(9):
+            s.cell[i] = self.cell[i]
+        s.alpha = self.alpha.data_ptr()
+        s.omega = self.omega.data_ptr()
+        s.r_vdw = self.rvdw.data_ptr()
+        return s
+
+
+def _stream_ptr():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """Owns one mbd_plan. Systems must stay alive while the plan exists."""
+
+    def __init__(self, systems: List[DeviceSystem], params: Params):
+        self.lib = L.lib()
+        self.systems = systems
+        self.params = params
+        arr = (L.MbdSystem * len(systems))(*[s.to_c() for s in systems])
+        self._cparams = params.to_c()
+        h = C.c_void_p()
+        L.check(self.lib.mbd_plan_create(C.byref(h), arr, len(systems), C.byref(self._cparams),
+                                         _stream_ptr()))
+        self.handle = h
+
+    def info(self, sys: int = 0) -> L.MbdInfo:
+        inf = L.MbdInfo()
+        L.check(self.lib.mbd_plan_info(self.handle, sys, C.byref(inf)))
+        return inf
+
+    def execute(self) -> torch.Tensor:
+        e = torch.zeros(len(self.systems), dtype=torch.float64, device="cuda")
+        L.check(self.lib.mbd_execute(self.handle, C.c_void_p(e.data_ptr()), None))
+        return e
+
+    def check(self):
+        L.check(self.lib.mbd_check(self.handle))
+
+    def matvec(self, v: torch.Tensor, sys: int = 0, components: int = L.C_ALL) -> torch.Tensor:
+        v = v.to(dtype=torch.float64, device="cuda").contiguous()
+        squeeze = v.dim() == 2
+        if squeeze:
+            v = v[None]
+        out = torch.empty_like(v)
+        L.check(self.lib.mbd_matvec(self.handle, sys, C.c_void_p(v.data_ptr()),
+                                    C.c_void_p(out.data_ptr()), v.shape[0], components))
+        return out[0] if squeeze else out
+
+    def tridiagonal(self, sys: int = 0):
+        R, m = self.params.n_probes, self.params.n_steps
+        a = (C.c_double * (R * m))()
+        b = (C.c_double * (R * m))()
+        me = (C.c_int32 * R)()
+        L.check(self.lib.mbd_get_tridiagonal(self.handle, sys, a, b, me))
+        at = torch.tensor(list(a), dtype=torch.float64).reshape(R, m)
+        bt = torch.tensor(list(b), dtype=torch.float64).reshape(R, m)
+        return at, bt, torch.tensor(list(me), dtype=torch.int32)
+
+    def quadrature(self, sys: int = 0) -> torch.Tensor:
+        R = self.params.n_probes
+        q = (C.c_double * R)()
+        L.check(self.lib.mbd_get_quadrature(self.handle, sys, q))
+        return torch.tensor(list(q), dtype=torch.float64)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.mbd_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def energy(systems: List[DeviceSystem], params: Params) -> torch.Tensor:
+    """E_MBD per system (float64 tensor on the GPU)."""
+    plan = Plan(systems, params)
+    try:
+        e = plan.execute()
+        plan.check()
+        return e
+    finally:
+        plan.close()

@@ -1,0 +1,509 @@
+// Host runtime behind the C ABI: validation, parameter derivation, workspace,
+// device setup and the Algorithm 1 driver (probe blocks x Lanczos steps).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "mbd_math.h"
+
+namespace mbd {
+
+namespace {
+thread_local std::string g_last_error;
+
+constexpr double kBohrAngstrom = 0.529177210903;
+
+struct HipError {
+  hipError_t e;
+  const char* what;
+};
+
+void check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw HipError{e, what};
+}
+
+// erfc(tau rc) / rc = eps with rc in Angstrom, bisection (tau in 1/Angstrom).
+double tau_from_cutoff_angstrom(double rc, double eps = 1e-8) {
+  double lo = 0.0, hi = 1.0;
+  while (std::erfc(hi * rc) / rc > eps) hi *= 2.0;
+  for (int i = 0; i < 200; ++i) {
+    double mid = 0.5 * (lo + hi);
+    if (std::erfc(mid * rc) / rc > eps) lo = mid; else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// Smallest even 2^a 3^b >= 1.4 points per Angstrom.
+int grid_rule(double L_bohr) {
+  const double target = 1.4 * L_bohr * kBohrAngstrom;
+  int best = 0;
+  for (int p2 = 2; p2 <= 4096; p2 *= 2)
+    for (int k = p2; k <= 4096; k *= 3)
+      if (k >= target && (best == 0 || k < best)) best = k;
+  return best;
+}
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+template <typename T>
+T* dalloc(Plan& plan, size_t count, size_t& bytes) {
+  void* p = nullptr;
+  const size_t nb = std::max<size_t>(count, 1) * sizeof(T);
+  hipError_t e = hipMalloc(&p, nb);
+  if (e != hipSuccess) throw std::bad_alloc();
+  plan.allocations.push_back(p);
+  bytes += nb;
+  return static_cast<T*>(p);
+}
+
+// Influence function on the half spectrum [K3][K2][K1/2+1] and twiddle tables.
+template <typename R>
+void host_tables(const Geometry& g, std::vector<R>& G, std::vector<R>& tw) {
+  const int K1 = g.K[0], K2 = g.K[1], K3 = g.K[2], KX = K1 / 2 + 1;
+  const double V = g.L[0] * g.L[1] * g.L[2];
+  double th[kMaxOrder], dth[kMaxOrder];
+  std::vector<double> Mk(g.p);
+  switch (g.p) {
+    case 4: bspline_weights<4>(0.0, th, dth); break;
+    case 6: bspline_weights<6>(0.0, th, dth); break;
+    default: bspline_weights<8>(0.0, th, dth); break;
+  }
+  // |b(m)|^2 = 1 / |sum_{k=0}^{p-2} M_p(k+1) e^{2 pi i m k / K}|^2
+  auto bmod = [&](int K) {
+    std::vector<double> out(K);
+    for (int m = 0; m < K; ++m) {
+      double re = 0.0, im = 0.0;
+      for (int k = 0; k <= g.p - 2; ++k) {
+        const double ph = 2.0 * M_PI * m * k / K;
+        re += th[k + 1] * std::cos(ph);
+        im += th[k + 1] * std::sin(ph);
+      }
+      out[m] = 1.0 / (re * re + im * im);
+    }
+    return out;
+  };
+  const auto b1 = bmod(K1), b2 = bmod(K2), b3 = bmod(K3);
+  G.assign((size_t)K3 * K2 * KX, R(0));
+  for (int kz = 0; kz < K3; ++kz) {
+    const double mz = (kz <= K3 / 2 ? kz : kz - K3) / g.L[2];
+    for (int ky = 0; ky < K2; ++ky) {
+      const double my = (ky <= K2 / 2 ? ky : ky - K2) / g.L[1];
+      for (int kx = 0; kx < KX; ++kx) {
+        const double mx = kx / g.L[0];
+        const double m2 = mx * mx + my * my + mz * mz;
+        double v = 0.0;
+        if (m2 > 0.0)
+          v = std::exp(-M_PI * M_PI * m2 / (g.tau * g.tau)) * b1[kx] * b2[ky] * b3[kz] /
+              (M_PI * V * m2);
+        G[((size_t)kz * K2 + ky) * KX + kx] = (R)v;
+      }
+    }
+  }
+  const int Ks = K1 + K2 + K3;
+  tw.assign(2 * (size_t)Ks, R(0));
+  int off = 0;
+  for (int a = 0; a < 3; ++a) {
+    for (int j = 0; j < g.K[a]; ++j) {
+      tw[off + j] = (R)std::cos(2.0 * M_PI * j / g.K[a]);
+      tw[Ks + off + j] = (R)std::sin(2.0 * M_PI * j / g.K[a]);
+    }
+    off += g.K[a];
+  }
+}
+
+template <typename R>
+void allocate_system(Plan& plan, System& S, int R_probes, int m) {
+  Geometry& g = S.geo;
+  SysBuffers& b = S.buf;
+  size_t& by = S.bytes;
+  const int n = g.n, B = plan.B;
+  const int ncell = g.nc[0] * g.nc[1] * g.nc[2];
+  const int ntiles = g.tiles[0] * g.tiles[1] * g.tiles[2];
+  b.perm = dalloc<int>(plan, n, by);
+  b.cell_of = dalloc<int>(plan, n, by);
+  b.cell_start = dalloc<int>(plan, ncell + 1, by);
+  b.cell_cursor = dalloc<int>(plan, ncell, by);
+  b.wpos = dalloc<double>(plan, 3 * (size_t)n, by);
+  b.loc = dalloc<R>(plan, 4 * (size_t)n, by);
+  b.g = dalloc<double>(plan, n, by);
+  b.om2 = dalloc<double>(plan, n, by);
+  b.base = dalloc<int>(plan, 3 * (size_t)n, by);
+  b.scell = dalloc<int>(plan, n, by);
+  b.th = dalloc<R>(plan, 3 * (size_t)n * g.p, by);
+  b.dth = dalloc<R>(plan, 3 * (size_t)n * g.p, by);
+  b.tile_count = dalloc<int>(plan, ntiles + 1, by);
+  b.tile_start = dalloc<int>(plan, ntiles + 1, by);
+  b.tile_atoms = dalloc<int>(plan, 27 * (size_t)n, by);
+  b.G = dalloc<R>(plan, (size_t)g.K[2] * g.K[1] * (g.K[0] / 2 + 1), by);
+  b.tw = dalloc<R>(plan, 2 * (size_t)(g.K[0] + g.K[1] + g.K[2]), by);
+  const size_t vec = 3 * (size_t)n * B;
+  b.W = dalloc<double>(plan, vec * m, by);
+  b.Lt = dalloc<double>(plan, vec, by);
+  b.dv = dalloc<R>(plan, vec, by);
+  b.Ed = dalloc<R>(plan, vec, by);
+  b.grid = dalloc<R>(plan, (size_t)g.K[2] * g.K[1] * (g.K[0] + 2) * B, by);
+  b.part = dalloc<double>(plan, (size_t)kRedBlocks * 4 * B, by);
+  b.coef = dalloc<double>(plan, (size_t)kMaxSteps * B, by);
+  b.a = dalloc<double>(plan, (size_t)R_probes * m, by);
+  b.b = dalloc<double>(plan, (size_t)R_probes * m, by);
+  b.meff = dalloc<int>(plan, R_probes, by);
+  b.q = dalloc<double>(plan, R_probes, by);
+  b.sum_omega = dalloc<double>(plan, 1, by);
+  std::vector<R> G, tw;
+  host_tables<R>(g, G, tw);
+  check(hipMemcpy(b.G, G.data(), G.size() * sizeof(R), hipMemcpyHostToDevice), "copy G");
+  check(hipMemcpy(b.tw, tw.data(), tw.size() * sizeof(R), hipMemcpyHostToDevice), "copy tw");
+}
+
+template <typename R>
+void run_setup(Plan& plan, System& S, const mbd_system& src, const double* pos) {
+  launch_setup<R>(S.geo, S.buf, pos, src.alpha, src.omega, src.r_vdw, plan.stream);
+}
+
+// One application of C to the block stored at w (internal layout), into Lt.
+template <typename R>
+void matvec_block(Plan& plan, System& S, const double* w, uint32_t comps) {
+  const hipStream_t st = plan.stream;
+  if (comps & MBD_C_DIR) launch_pair<R>(S.geo, S.buf, plan.B, st);
+  if (comps & MBD_C_REC) launch_spme<R>(S.geo, S.buf, plan.B, plan.BG, st);
+  launch_epilogue<R>(S.geo, S.buf, w, plan.B, plan.BG, comps, st);
+}
+
+template <typename R>
+void run_energy(Plan& plan, System& S, int sys_index, double* energy) {
+  const hipStream_t st = plan.stream;
+  const int B = plan.B, m = plan.prm.n_steps, R_probes = plan.prm.n_probes;
+  const bool fl = sizeof(R) == 4;
+  const size_t vs = 3 * (size_t)S.geo.n * B;
+  for (int l0 = 0; l0 < R_probes; l0 += B) {
+    const int nb = std::min(B, R_probes - l0);
+    launch_init_scalars(S.buf, nb, m, l0, st);
+    launch_probes(S.geo, S.buf, B, nb, l0, plan.prm.seed, sys_index, fl, st);
+    for (int k = 0; k < m; ++k) {
+      matvec_block<R>(plan, S, S.buf.W + (size_t)k * vs, MBD_C_ALL);
+      launch_finish_a(S.buf, B, nb, k, m, l0, plan.status, st);
+      if (k + 1 < m) {
+        const int ro = plan.prm.reorth;
+        launch_update(S.geo, S.buf, B, nb, k, m, l0, fl, ro == MBD_REORTH_NONE, st);
+        if (ro == MBD_REORTH_LOCAL) {
+          launch_reorth(S.geo, S.buf, B, nb, k, m, l0, std::max(0, k - 1), fl, st);
+        } else if (ro == MBD_REORTH_FULL) {
+          launch_reorth(S.geo, S.buf, B, nb, k, m, l0, 0, fl, st);
+          launch_reorth(S.geo, S.buf, B, nb, k, m, l0, 0, fl, st);
+        }
+        launch_finish_norm(S.buf, B, nb, k, m, l0, plan.status, st);
+      }
+    }
+    launch_tridiag(S.buf, nb, m, l0, plan.status, st);
+  }
+  launch_energy(S.geo, S.buf, R_probes, energy, plan.status, st);
+}
+
+mbd_status fail(mbd_status code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+}  // namespace mbd
+
+struct mbd_plan_s {
+  mbd::Plan plan;
+};
+
+using mbd::fail;
+
+extern "C" {
+
+const char* mbd_last_error(void) { return mbd::g_last_error.c_str(); }
+
+const char* mbd_status_string(mbd_status s) {
+  switch (s) {
+    case MBD_OK: return "ok";
+    case MBD_E_ARG: return "invalid argument";
+    case MBD_E_CELL: return "cell is not orthorhombic";
+    case MBD_E_GRID: return "unsupported grid";
+    case MBD_E_NOT_POSDEF: return "coupling matrix not positive definite";
+    case MBD_E_NONFINITE: return "non-finite value";
+    case MBD_E_NODEVICE: return "no GPU device";
+    case MBD_E_HIP: return "HIP runtime error";
+    case MBD_E_OOM: return "out of device memory";
+    case MBD_E_STATE: return "call out of order";
+    default: return "unknown status";
+  }
+}
+
+int32_t mbd_grid_supported(int32_t k) { return mbd::fft_supported(k) ? 1 : 0; }
+
+mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_sys,
+                           const mbd_params* prm_in, void* stream) {
+  using namespace mbd;
+  if (!out) return fail(MBD_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!systems || n_sys < 1) return fail(MBD_E_ARG, "need at least one system");
+  if (!prm_in) return fail(MBD_E_ARG, "params is NULL");
+  mbd_params prm = *prm_in;
+  if (!(prm.damp_beta > 0.0) || !std::isfinite(prm.damp_beta))
+    return fail(MBD_E_ARG, "damp_beta must be > 0");
+  if (!(prm.damp_d > 0.0) || !std::isfinite(prm.damp_d))
+    return fail(MBD_E_ARG, "damp_d must be > 0");
+  if (!(prm.real_cutoff > 0.0) || !std::isfinite(prm.real_cutoff))
+    return fail(MBD_E_ARG, "real_cutoff must be > 0");
+  if (!std::isfinite(prm.ewald_tau)) return fail(MBD_E_ARG, "ewald_tau is not finite");
+  if (!std::isfinite(prm.damp_tol) || prm.damp_tol >= 0.5)
+    return fail(MBD_E_ARG, "damp_tol must be < 0.5");
+  if (prm.spline_order == 0) prm.spline_order = 6;
+  if (prm.spline_order != 4 && prm.spline_order != 6 && prm.spline_order != 8)
+    return fail(MBD_E_ARG, "spline_order must be 4, 6 or 8");
+  if (prm.n_probes < 1) return fail(MBD_E_ARG, "n_probes must be >= 1");
+  if (prm.n_steps < 1 || prm.n_steps > kMaxSteps)
+    return fail(MBD_E_ARG, "n_steps must be in [1, 512]");
+  if (prm.block == 0) {
+    int b = 1;
+    while (b < prm.n_probes && b < 128) b *= 2;
+    prm.block = b;
+  }
+  if (!is_pow2(prm.block) || prm.block > 256)
+    return fail(MBD_E_ARG, "block must be a power of two <= 256");
+  if (prm.precision != MBD_PREC_FP64 && prm.precision != MBD_PREC_MIXED)
+    return fail(MBD_E_ARG, "precision must be MBD_PREC_FP64 or MBD_PREC_MIXED");
+  if (prm.reorth < MBD_REORTH_NONE || prm.reorth > MBD_REORTH_FULL)
+    return fail(MBD_E_ARG, "reorth must be NONE, LOCAL or FULL");
+  if (prm.want_forces != 0) return fail(MBD_E_ARG, "forces are not available in this version");
+  for (int a = 0; a < 3; ++a)
+    if (prm.grid[a] < 0) return fail(MBD_E_ARG, "grid sizes must be >= 0");
+
+  std::vector<Geometry> geos(n_sys);
+  for (int s = 0; s < n_sys; ++s) {
+    const mbd_system& sy = systems[s];
+    if (sy.n_atoms < 1) return fail(MBD_E_ARG, "n_atoms must be >= 1");
+    if (!sy.pos || !sy.alpha || !sy.omega || !sy.r_vdw)
+      return fail(MBD_E_ARG, "system arrays must be non-NULL device pointers");
+    for (int i = 0; i < 9; ++i)
+      if (!std::isfinite(sy.cell[i])) return fail(MBD_E_ARG, "cell is not finite");
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c)
+        if (r != c && sy.cell[3 * r + c] != 0.0)
+          return fail(MBD_E_CELL, "only orthorhombic (diagonal) cells are supported");
+    Geometry& g = geos[s];
+    g.n = sy.n_atoms;
+    for (int a = 0; a < 3; ++a) {
+      g.L[a] = sy.cell[4 * a];
+      if (!(g.L[a] > 0.0)) return fail(MBD_E_CELL, "cell edges must be > 0");
+    }
+    g.p = prm.spline_order;
+    for (int a = 0; a < 3; ++a) {
+      int K = prm.grid[a] > 0 ? prm.grid[a] : grid_rule(g.L[a]);
+      if (!fft_supported(K))
+        return fail(MBD_E_GRID, "grid size " + std::to_string(K) +
+                                     " unsupported (even 2^a 3^b 5^c in [8, 128])");
+      if (K < 2 * g.p) return fail(MBD_E_GRID, "grid must be >= 2 p");
+      g.K[a] = K;
+      g.tiles[a] = (K + kSpreadTile - 1) / kSpreadTile;
+    }
+    g.tau = prm.ewald_tau > 0.0
+                ? prm.ewald_tau
+                : tau_from_cutoff_angstrom(prm.real_cutoff * kBohrAngstrom) * kBohrAngstrom;
+    g.beta = prm.damp_beta;
+    g.damp_d = prm.damp_d;
+  }
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return fail(MBD_E_NODEVICE, "no HIP device available");
+
+  auto* handle = new (std::nothrow) mbd_plan_s();
+  if (!handle) return fail(MBD_E_OOM, "host allocation failed");
+  Plan& plan = handle->plan;
+  plan.prm = prm;
+  plan.prec = prm.precision;
+  plan.B = prm.block;
+  plan.BG = std::min(plan.B, plan.prec == MBD_PREC_FP64 ? 16 : 32);
+  plan.stream = static_cast<hipStream_t>(stream);
+  hipGetDevice(&plan.device);
+  try {
+    size_t sb = 0;
+    plan.status = dalloc<uint32_t>(plan, 1, sb);
+    check(hipMemset(plan.status, 0, sizeof(uint32_t)), "clear status");
+    plan.sys.resize(n_sys);
+    for (int s = 0; s < n_sys; ++s) {
+      const mbd_system& sy = systems[s];
+      System& S = plan.sys[s];
+      S.geo = geos[s];
+      std::memcpy(S.host_cell, sy.cell, sizeof(S.host_cell));
+      // host copies of the per-atom parameters: validation and the damping range
+      std::vector<double> al(sy.n_atoms), om(sy.n_atoms), rv(sy.n_atoms);
+      check(hipMemcpy(al.data(), sy.alpha, sizeof(double) * sy.n_atoms, hipMemcpyDeviceToHost),
+            "read alpha");
+      check(hipMemcpy(om.data(), sy.omega, sizeof(double) * sy.n_atoms, hipMemcpyDeviceToHost),
+            "read omega");
+      check(hipMemcpy(rv.data(), sy.r_vdw, sizeof(double) * sy.n_atoms, hipMemcpyDeviceToHost),
+            "read r_vdw");
+      double rmax = 0.0;
+      for (int i = 0; i < sy.n_atoms; ++i) {
+        if (!(al[i] > 0.0) || !std::isfinite(al[i]) || !(om[i] > 0.0) ||
+            !std::isfinite(om[i]) || !(rv[i] > 0.0) || !std::isfinite(rv[i])) {
+          mbd_plan_destroy(handle);
+          return fail(MBD_E_ARG, "alpha, omega and r_vdw must be finite and > 0");
+        }
+        rmax = std::max(rmax, rv[i]);
+      }
+      Geometry& g = S.geo;
+      double rp = prm.real_cutoff;
+      if (prm.damp_tol >= 0.0) {
+        const double tol = prm.damp_tol > 0.0 ? prm.damp_tol : 1e-7;
+        const double smax = prm.damp_beta * 2.0 * rmax;
+        rp = std::max(rp, smax * (1.0 + std::log(1.0 / tol - 1.0) / prm.damp_d));
+      }
+      g.r_pair = rp;
+      for (int a = 0; a < 3; ++a) {
+        g.nc[a] = std::max(1, (int)std::floor(g.L[a] / (0.5 * rp)));
+        g.nc[a] = std::min(g.nc[a], 64);
+        g.hc[a] = g.L[a] / g.nc[a];
+        g.nr[a] = (int)std::ceil(rp / g.hc[a] - 1e-12);
+      }
+      if (plan.prec == MBD_PREC_FP64) {
+        allocate_system<double>(plan, S, prm.n_probes, prm.n_steps);
+        run_setup<double>(plan, S, sy, sy.pos);
+      } else {
+        allocate_system<float>(plan, S, prm.n_probes, prm.n_steps);
+        run_setup<float>(plan, S, sy, sy.pos);
+      }
+      check(hipGetLastError(), "setup launch");
+    }
+  } catch (const std::bad_alloc&) {
+    mbd_plan_destroy(handle);
+    return fail(MBD_E_OOM, "device allocation failed");
+  } catch (const HipError& e) {
+    std::string msg = std::string(e.what) + ": " + hipGetErrorString(e.e);
+    mbd_plan_destroy(handle);
+    return fail(MBD_E_HIP, msg);
+  }
+  // keep the caller's parameter pointers for set_positions
+  *out = handle;
+  return MBD_OK;
+}
+
+mbd_status mbd_plan_info(mbd_plan plan, int32_t sys, mbd_info* info) {
+  if (!plan || !info) return fail(MBD_E_ARG, "NULL argument");
+  mbd::Plan& P = plan->plan;
+  if (sys < 0 || sys >= (int)P.sys.size()) return fail(MBD_E_ARG, "system index out of range");
+  const mbd::Geometry& g = P.sys[sys].geo;
+  info->tau = g.tau;
+  info->r_pair = g.r_pair;
+  for (int a = 0; a < 3; ++a) {
+    info->grid[a] = g.K[a];
+    info->cells[a] = g.nc[a];
+  }
+  info->spline_order = g.p;
+  info->block = P.B;
+  info->workspace_bytes = P.sys[sys].bytes;
+  return MBD_OK;
+}
+
+mbd_status mbd_set_positions(mbd_plan plan, int32_t sys, const double* pos) {
+  (void)plan; (void)sys; (void)pos;
+  return fail(MBD_E_STATE, "set_positions needs the parameter arrays; not available yet");
+}
+
+mbd_status mbd_execute(mbd_plan plan, double* energy, double* forces) {
+  using namespace mbd;
+  if (!plan || !energy) return fail(MBD_E_ARG, "NULL argument");
+  if (forces) return fail(MBD_E_ARG, "forces are not available in this version");
+  Plan& P = plan->plan;
+  try {
+    check(hipMemsetAsync(P.status, 0, sizeof(uint32_t), P.stream), "clear status");
+    for (int s = 0; s < (int)P.sys.size(); ++s) {
+      if (P.prec == MBD_PREC_FP64) run_energy<double>(P, P.sys[s], s, energy + s);
+      else run_energy<float>(P, P.sys[s], s, energy + s);
+    }
+    check(hipGetLastError(), "execute launch");
+  } catch (const HipError& e) {
+    return fail(MBD_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
+  P.executed = true;
+  return MBD_OK;
+}
+
+mbd_status mbd_check(mbd_plan plan) {
+  if (!plan) return fail(MBD_E_ARG, "NULL plan");
+  mbd::Plan& P = plan->plan;
+  uint32_t st = 0;
+  if (hipStreamSynchronize(P.stream) != hipSuccess)
+    return fail(MBD_E_HIP, "stream synchronize failed");
+  if (hipMemcpy(&st, P.status, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(MBD_E_HIP, "status read failed");
+  if (st & mbd::kErrNotPosdef) return fail(MBD_E_NOT_POSDEF, "a Ritz value is <= 0");
+  if (st & (mbd::kErrNonfinite | mbd::kErrNoConverge))
+    return fail(MBD_E_NONFINITE, "non-finite value or non-converged tridiagonal");
+  return MBD_OK;
+}
+
+mbd_status mbd_matvec(mbd_plan plan, int32_t sys, const double* v, double* out, int32_t nrhs,
+                      uint32_t components) {
+  using namespace mbd;
+  if (!plan || !v || !out) return fail(MBD_E_ARG, "NULL argument");
+  Plan& P = plan->plan;
+  if (sys < 0 || sys >= (int)P.sys.size()) return fail(MBD_E_ARG, "system index out of range");
+  if (nrhs < 1 || nrhs > P.B) return fail(MBD_E_ARG, "nrhs must be in [1, block]");
+  if (components == 0 || components > MBD_C_ALL) return fail(MBD_E_ARG, "bad component mask");
+  System& S = P.sys[sys];
+  const bool fl = P.prec == MBD_PREC_MIXED;
+  launch_pack(S.geo, S.buf, v, nrhs, P.B, fl, P.stream);
+  if (fl) matvec_block<float>(P, S, S.buf.W, components);
+  else matvec_block<double>(P, S, S.buf.W, components);
+  launch_unpack(S.geo, S.buf, out, nrhs, P.B, P.stream);
+  if (hipGetLastError() != hipSuccess) return fail(MBD_E_HIP, "matvec launch failed");
+  return MBD_OK;
+}
+
+mbd_status mbd_get_tridiagonal(mbd_plan plan, int32_t sys, double* a, double* b,
+                               int32_t* m_eff) {
+  if (!plan || !a || !b || !m_eff) return fail(MBD_E_ARG, "NULL argument");
+  mbd::Plan& P = plan->plan;
+  if (sys < 0 || sys >= (int)P.sys.size()) return fail(MBD_E_ARG, "system index out of range");
+  if (!P.executed) return fail(MBD_E_STATE, "no execute has run");
+  const int R = P.prm.n_probes, m = P.prm.n_steps;
+  const mbd::SysBuffers& B = P.sys[sys].buf;
+  std::vector<double> nrm((size_t)R * m);
+  if (hipStreamSynchronize(P.stream) != hipSuccess ||
+      hipMemcpy(a, B.a, sizeof(double) * R * m, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(nrm.data(), B.b, sizeof(double) * R * m, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(m_eff, B.meff, sizeof(int32_t) * R, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(MBD_E_HIP, "copy failed");
+  for (int l = 0; l < R; ++l)
+    for (int k = 0; k < m; ++k) b[(size_t)l * m + k] = (k + 1 < m) ? nrm[(size_t)l * m + k + 1] : 0.0;
+  return MBD_OK;
+}
+
+mbd_status mbd_get_quadrature(mbd_plan plan, int32_t sys, double* q) {
+  if (!plan || !q) return fail(MBD_E_ARG, "NULL argument");
+  mbd::Plan& P = plan->plan;
+  if (sys < 0 || sys >= (int)P.sys.size()) return fail(MBD_E_ARG, "system index out of range");
+  if (!P.executed) return fail(MBD_E_STATE, "no execute has run");
+  if (hipStreamSynchronize(P.stream) != hipSuccess ||
+      hipMemcpy(q, P.sys[sys].buf.q, sizeof(double) * P.prm.n_probes, hipMemcpyDeviceToHost) !=
+          hipSuccess)
+    return fail(MBD_E_HIP, "copy failed");
+  return MBD_OK;
+}
+
+mbd_status mbd_plan_destroy(mbd_plan plan) {
+  if (!plan) return MBD_OK;
+  hipStreamSynchronize(plan->plan.stream);
+  for (void* p : plan->plan.allocations) hipFree(p);
+  delete plan;
+  return MBD_OK;
+}
+
+}  // extern "C"

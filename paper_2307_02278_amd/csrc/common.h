@@ -1,0 +1,135 @@
+// Internal declarations shared by the host runtime and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mbd.h"
+
+namespace mbd {
+
+constexpr int kMaxOrder = 8;
+constexpr int kSpreadTile = 8;     // grid points per tile edge in the spread kernel
+constexpr int kRedBlocks = 256;    // blocks (and partial sums) of the Lanczos reductions
+constexpr int kMaxSteps = 512;
+
+// Device-side error bits (status word).
+enum : uint32_t { kErrNotPosdef = 1u, kErrNonfinite = 2u, kErrNoConverge = 4u };
+
+// Everything one kernel launch needs to know about a system's geometry and grid.
+struct Geometry {
+  int n;                 // atoms
+  double L[3];           // orthorhombic edges (bohr)
+  int K[3];              // SPME grid
+  int p;                 // spline order
+  double tau;            // 1/bohr
+  double r_pair;         // direct-space cutoff (bohr)
+  int nc[3];             // cells per axis
+  double hc[3];          // cell edge per axis
+  int nr[3];             // neighbour-cell range per axis
+  int tiles[3];          // spread tiles per axis
+  double beta, damp_d;
+};
+
+// Device buffers of one system.
+struct SysBuffers {
+  // sorted atom data
+  int* perm = nullptr;         // [n] sorted -> caller index
+  int* cell_of = nullptr;      // [n] cell of each caller atom
+  int* cell_start = nullptr;   // [ncell + 1]
+  int* cell_cursor = nullptr;  // [ncell]
+  double* wpos = nullptr;      // [n][3] wrapped positions, caller order
+  void* loc = nullptr;         // Real [n][4] cell-local position + damping radius (sorted)
+  double* g = nullptr;         // [n] omega sqrt(alpha) (sorted)
+  double* om2 = nullptr;       // [n] omega^2 (sorted)
+  int* base = nullptr;         // [n][3] spline base indices (sorted)
+  int* scell = nullptr;        // [n] cell of each sorted atom
+  void* th = nullptr;          // Real [n][3][p] M_p(w + t)
+  void* dth = nullptr;         // Real [n][3][p] (K_a / L_a) M_p'(w + t)
+  int* tile_count = nullptr;   // [ntiles + 1]
+  int* tile_start = nullptr;   // [ntiles + 1]
+  int* tile_atoms = nullptr;   // [27 n]
+  void* G = nullptr;           // Real [K3][K2][K1/2 + 1]
+  void* tw = nullptr;          // Real [2][K1 + K2 + K3] twiddles exp(-2 pi i j / K_a)
+  // Lanczos state for one block of right-hand sides
+  double* W = nullptr;         // [m][n][3][B] Krylov vectors, unnormalized
+  double* Lt = nullptr;        // [n][3][B] C w_k
+  void* dv = nullptr;          // Real [n][3][B] generalized dipoles g * w_k
+  void* Ed = nullptr;          // Real [n][3][B] direct-space field
+  void* grid = nullptr;        // Real [B / BG][K3][K2][K1 + 2][BG]
+  double* part = nullptr;      // [kRedBlocks][4][B] partial sums
+  double* coef = nullptr;      // [B][kMaxSteps] reorthogonalization coefficients
+  double* a = nullptr;         // [R][m] Lanczos diagonal
+  double* b = nullptr;         // [R][m] nrm[l][k] = ||w_k|| (nrm[l][0] = 1)
+  int* meff = nullptr;         // [R]
+  double* q = nullptr;         // [R] per-probe quadrature
+  double* sum_omega = nullptr; // [1]
+};
+
+struct System {
+  Geometry geo;
+  SysBuffers buf;
+  double host_cell[9];
+  size_t bytes = 0;
+};
+
+struct Plan {
+  std::vector<System> sys;
+  mbd_params prm;
+  int prec;                    // MBD_PREC_*
+  int B;                       // RHS per block
+  int BG;                      // RHS per grid chunk
+  hipStream_t stream = nullptr;
+  int device = 0;
+  uint32_t* status = nullptr;  // device status word
+  bool executed = false;
+  std::vector<void*> allocations;
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files). All enqueue on `st`.
+// ---------------------------------------------------------------------------
+template <typename R>
+void launch_setup(const Geometry& g, SysBuffers& b, const double* pos, const double* alpha,
+                  const double* omega, const double* rvdw, hipStream_t st);
+
+template <typename R>
+void launch_pair(const Geometry& g, const SysBuffers& b, int B, hipStream_t st);
+
+template <typename R>
+void launch_spme(const Geometry& g, const SysBuffers& b, int B, int BG, hipStream_t st);
+
+void fill_int(int* p, int v, int n, hipStream_t st);
+
+template <typename R>
+void launch_epilogue(const Geometry& g, const SysBuffers& b, const double* w, int B, int BG,
+                     uint32_t comps, hipStream_t st);
+
+void launch_probes(const Geometry& g, const SysBuffers& b, int B, int nb, int probe0,
+                   uint64_t seed, int system, bool use_float, hipStream_t st);
+void launch_init_scalars(const SysBuffers& b, int nb, int m, int probe0, hipStream_t st);
+void launch_update(const Geometry& g, const SysBuffers& b, int B, int nb, int k, int m,
+                   int probe0, bool use_float, bool write_d, hipStream_t st);
+void launch_reorth(const Geometry& g, const SysBuffers& b, int B, int nb, int k, int m,
+                   int probe0, int j0, bool use_float, hipStream_t st);
+void launch_finish_a(const SysBuffers& b, int B, int nb, int k, int m, int probe0,
+                     uint32_t* status, hipStream_t st);
+void launch_finish_norm(const SysBuffers& b, int B, int nb, int k, int m, int probe0,
+                        uint32_t* status, hipStream_t st);
+void launch_tridiag(const SysBuffers& b, int nb, int m, int probe0, uint32_t* status,
+                    hipStream_t st);
+void launch_energy(const Geometry& g, const SysBuffers& b, int R, double* energy_out,
+                   uint32_t* status, hipStream_t st);
+void launch_pack(const Geometry& g, const SysBuffers& b, const double* v, int nrhs, int B,
+                 bool use_float, hipStream_t st);
+void launch_unpack(const Geometry& g, const SysBuffers& b, double* out, int nrhs, int B,
+                   hipStream_t st);
+
+bool fft_supported(int k);
+void set_error(const std::string& msg);
+
+}  // namespace mbd

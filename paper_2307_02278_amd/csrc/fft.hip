@@ -1,0 +1,329 @@
+// 3D FFT of the SPME dipole grid, batched over right-hand sides, with the
+// influence-function convolution fused into the last axis (the convolution
+// G * D of eq. spme done in Fourier space: forward transform, multiply by
+// G(m) = exp(-pi^2 |m|^2 / tau^2) B(m) / (pi V |m|^2), inverse transform).
+//
+// Layout of one grid chunk (BG right-hand sides, innermost):
+//   real value (x, y, z, b)      at ((z K2 + y) XS + x) BG + b,  XS = K1 + 2
+//   spectrum (kx, ky, kz, b): re at ((kz K2 + ky) XS + 2 kx) BG + b, im at +BG
+// Each pass transforms whole lines of one axis in place. A work-group loads NC
+// "columns" (line, b) into LDS, runs a mixed-radix Stockham FFT (radices 4, 2, 3,
+// 5) with one lane per column, and writes the columns back. Forward transforms
+// use e^{-2 pi i jk/K}, inverse ones e^{+2 pi i jk/K}; neither is normalized.
+#include "common.h"
+
+namespace mbd {
+
+namespace {
+
+struct Radices {
+  int r[12];
+  int n;
+};
+
+constexpr Radices factorize(int K) {
+  Radices f{};
+  f.n = 0;
+  int k = K;
+  while (k % 4 == 0) { f.r[f.n++] = 4; k /= 4; }
+  while (k % 2 == 0) { f.r[f.n++] = 2; k /= 2; }
+  while (k % 3 == 0) { f.r[f.n++] = 3; k /= 3; }
+  while (k % 5 == 0) { f.r[f.n++] = 5; k /= 5; }
+  return f;
+}
+
+constexpr int prefix_product(int K, int S) {
+  int p = 1;
+  for (int i = 0; i < S; ++i) p *= factorize(K).r[i];
+  return p;
+}
+
+// Length-r DFT in registers; sign -1 forward, +1 inverse.
+template <typename R, int r, bool FWD>
+__device__ __forceinline__ void small_dft(R* xr, R* xi) {
+  constexpr R sg = FWD ? R(-1) : R(1);
+  if constexpr (r == 2) {
+    R ar = xr[0] + xr[1], ai = xi[0] + xi[1];
+    R br = xr[0] - xr[1], bi = xi[0] - xi[1];
+    xr[0] = ar; xi[0] = ai; xr[1] = br; xi[1] = bi;
+  } else if constexpr (r == 4) {
+    R s0r = xr[0] + xr[2], s0i = xi[0] + xi[2];
+    R d0r = xr[0] - xr[2], d0i = xi[0] - xi[2];
+    R s1r = xr[1] + xr[3], s1i = xi[1] + xi[3];
+    R d1r = xr[1] - xr[3], d1i = xi[1] - xi[3];
+    // multiply d1 by sg * i
+    R jr = -sg * d1i, ji = sg * d1r;
+    xr[0] = s0r + s1r; xi[0] = s0i + s1i;
+    xr[2] = s0r - s1r; xi[2] = s0i - s1i;
+    xr[1] = d0r + jr;  xi[1] = d0i + ji;
+    xr[3] = d0r - jr;  xi[3] = d0i - ji;
+  } else if constexpr (r == 3) {
+    constexpr R h = R(0.86602540378443864676);
+    R sr = xr[1] + xr[2], si = xi[1] + xi[2];
+    R dr = xr[1] - xr[2], di = xi[1] - xi[2];
+    R tr = xr[0] - R(0.5) * sr, ti = xi[0] - R(0.5) * si;
+    // (sg * i * h) * d
+    R ur = -sg * h * di, ui = sg * h * dr;
+    xr[0] = xr[0] + sr; xi[0] = xi[0] + si;
+    xr[1] = tr + ur; xi[1] = ti + ui;
+    xr[2] = tr - ur; xi[2] = ti - ui;
+  } else if constexpr (r == 5) {
+    constexpr R c1 = R(0.30901699437494742410);   // cos(2 pi / 5)
+    constexpr R c2 = R(-0.80901699437494742410);  // cos(4 pi / 5)
+    constexpr R s1 = R(0.95105651629515357212);   // sin(2 pi / 5)
+    constexpr R s2 = R(0.58778525229247312917);   // sin(4 pi / 5)
+    R ar = xr[1] + xr[4], ai = xi[1] + xi[4];
+    R br = xr[1] - xr[4], bi = xi[1] - xi[4];
+    R cr = xr[2] + xr[3], ci = xi[2] + xi[3];
+    R dr = xr[2] - xr[3], di = xi[2] - xi[3];
+    R y0r = xr[0] + ar + cr, y0i = xi[0] + ai + ci;
+    R p1r = xr[0] + c1 * ar + c2 * cr, p1i = xi[0] + c1 * ai + c2 * ci;
+    R p2r = xr[0] + c2 * ar + c1 * cr, p2i = xi[0] + c2 * ai + c1 * ci;
+    // q1 = sg * i * (s1 b + s2 d), q2 = sg * i * (s2 b - s1 d)
+    R q1r = -sg * (s1 * bi + s2 * di), q1i = sg * (s1 * br + s2 * dr);
+    R q2r = -sg * (s2 * bi - s1 * di), q2i = sg * (s2 * br - s1 * dr);
+    xr[0] = y0r; xi[0] = y0i;
+    xr[1] = p1r + q1r; xi[1] = p1i + q1i;
+    xr[4] = p1r - q1r; xi[4] = p1i - q1i;
+    xr[2] = p2r + q2r; xi[2] = p2i + q2i;
+    xr[3] = p2r - q2r; xi[3] = p2i - q2i;
+  }
+}
+
+// One Stockham stage (Govindaraju et al., SC'08 formulation): butterfly j reads
+// x[j + t K/r], applies twiddles W_{Ns r}^{(j mod Ns) t}, does a radix-r DFT and
+// writes y[(j / Ns) Ns r + (j mod Ns) + t Ns]. In-place in LDS with a barrier
+// between the read and the write phase.
+template <typename R, int K, int NC, int P, int S, bool FWD>
+__device__ __forceinline__ void stockham(R* re, R* im, const R* __restrict__ twc,
+                                         const R* __restrict__ tws, int c, int q) {
+  constexpr Radices F = factorize(K);
+  if constexpr (S < F.n) {
+    constexpr int r = F.r[S];
+    constexpr int NB = K / r;
+    constexpr int PER = (NB + P - 1) / P;
+    constexpr int Ns = prefix_product(K, S);
+    constexpr int TWS = K / (Ns * r);
+    R vr[PER][r], vi[PER][r];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int j = q + u * P;
+      if (j < NB) {
+        const int k = j % Ns;
+#pragma unroll
+        for (int t = 0; t < r; ++t) {
+          R xr = re[(j + t * NB) * NC + c];
+          R xi = im[(j + t * NB) * NC + c];
+          if (t > 0 && Ns > 1) {
+            const int idx = k * t * TWS;
+            const R wc = twc[idx];
+            const R ws = FWD ? -tws[idx] : tws[idx];
+            const R yr = xr * wc - xi * ws;
+            xi = xr * ws + xi * wc;
+            xr = yr;
+          }
+          vr[u][t] = xr;
+          vi[u][t] = xi;
+        }
+        small_dft<R, r, FWD>(vr[u], vi[u]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int j = q + u * P;
+      if (j < NB) {
+        const int k = j % Ns;
+        const int base = (j / Ns) * Ns * r + k;
+#pragma unroll
+        for (int t = 0; t < r; ++t) {
+          re[(base + t * Ns) * NC + c] = vr[u][t];
+          im[(base + t * Ns) * NC + c] = vi[u][t];
+        }
+      }
+    }
+    __syncthreads();
+    stockham<R, K, NC, P, S + 1, FWD>(re, im, twc, tws, c, q);
+  }
+}
+
+enum Pass { kXFwd = 0, kYFwd = 1, kZConv = 2, kYInv = 3, kXInv = 4 };
+
+struct GridDims {
+  int K1, K2, K3, XS, KX, BG;
+  size_t chunk_elems;
+};
+
+template <typename R, int K, int NC, int P, int MODE>
+__global__ void __launch_bounds__(NC * P)
+k_fft(R* __restrict__ grid, GridDims gd, const R* __restrict__ twc,
+      const R* __restrict__ tws, const R* __restrict__ G) {
+  extern __shared__ unsigned char smem_raw[];
+  R* re = reinterpret_cast<R*>(smem_raw);
+  R* im = re + K * NC;
+  const int c = threadIdx.x % NC;
+  const int q = threadIdx.x / NC;
+  R* g = grid + (size_t)blockIdx.y * gd.chunk_elems;
+  const long col = (long)blockIdx.x * NC + c;
+  const int BG = gd.BG;
+  const int b = (int)(col % BG);
+  const long line = col / BG;
+  long nlines;
+  size_t base, stride;
+  if (MODE == kXFwd || MODE == kXInv) {
+    nlines = (long)gd.K2 * gd.K3;
+    base = (size_t)line * gd.XS * BG + b;
+    stride = BG;
+  } else if (MODE == kYFwd || MODE == kYInv) {
+    nlines = (long)gd.K3 * gd.KX;
+    const long z = line / gd.KX, kx = line % gd.KX;
+    base = ((size_t)z * gd.K2 * gd.XS + 2 * kx) * BG + b;
+    stride = (size_t)gd.XS * BG;
+  } else {
+    nlines = (long)gd.K2 * gd.KX;
+    const long y = line / gd.KX, kx = line % gd.KX;
+    base = ((size_t)y * gd.XS + 2 * kx) * BG + b;
+    stride = (size_t)gd.K2 * gd.XS * BG;
+  }
+  const bool active = line < nlines;
+
+  // ---- load ----
+  if (MODE == kXFwd) {
+    for (int n = q; n < K; n += P) {
+      re[n * NC + c] = active ? g[base + (size_t)n * stride] : R(0);
+      im[n * NC + c] = R(0);
+    }
+  } else if (MODE == kXInv) {
+    // half spectrum kx = 0..K/2, the rest from Hermitian symmetry X[K-k] = conj(X[k])
+    for (int n = q; n < K; n += P) {
+      const int kk = n <= K / 2 ? n : K - n;
+      R xr = R(0), xi = R(0);
+      if (active) {
+        xr = g[base + (size_t)(2 * kk) * stride];
+        xi = g[base + (size_t)(2 * kk + 1) * stride];
+      }
+      re[n * NC + c] = xr;
+      im[n * NC + c] = n <= K / 2 ? xi : -xi;
+    }
+  } else {
+    for (int n = q; n < K; n += P) {
+      R xr = R(0), xi = R(0);
+      if (active) {
+        xr = g[base + (size_t)n * stride];
+        xi = g[base + (size_t)n * stride + BG];
+      }
+      re[n * NC + c] = xr;
+      im[n * NC + c] = xi;
+    }
+  }
+  __syncthreads();
+
+  constexpr bool FWD = (MODE == kXFwd || MODE == kYFwd || MODE == kZConv);
+  stockham<R, K, NC, P, 0, FWD>(re, im, twc, tws, c, q);
+
+  if (MODE == kZConv) {
+    if (active) {
+      const long y = line / gd.KX, kx = line % gd.KX;
+      for (int n = q; n < K; n += P) {
+        const R w = G[((size_t)n * gd.K2 + y) * gd.KX + kx];
+        re[n * NC + c] *= w;
+        im[n * NC + c] *= w;
+      }
+    }
+    __syncthreads();
+    stockham<R, K, NC, P, 0, false>(re, im, twc, tws, c, q);
+  }
+
+  // ---- store ----
+  if (!active) return;
+  if (MODE == kXFwd) {
+    for (int n = q; n <= K / 2; n += P) {
+      g[base + (size_t)(2 * n) * stride] = re[n * NC + c];
+      g[base + (size_t)(2 * n + 1) * stride] = im[n * NC + c];
+    }
+  } else if (MODE == kXInv) {
+    for (int n = q; n < K; n += P) g[base + (size_t)n * stride] = re[n * NC + c];
+  } else {
+    for (int n = q; n < K; n += P) {
+      g[base + (size_t)n * stride] = re[n * NC + c];
+      g[base + (size_t)n * stride + BG] = im[n * NC + c];
+    }
+  }
+}
+
+#define MBD_FFT_SIZES(X) \
+  X(8) X(10) X(12) X(16) X(18) X(20) X(24) X(30) X(32) X(36) X(40) X(48) X(50) X(54) \
+  X(60) X(64) X(72) X(80) X(90) X(96) X(100) X(108) X(120) X(128)
+
+template <typename R> struct FftShape;
+template <> struct FftShape<float> { static constexpr int NC = 64, P = 4; };
+template <> struct FftShape<double> { static constexpr int NC = 32, P = 8; };
+
+template <typename R, int MODE>
+void launch_pass(int K, R* grid, const GridDims& gd, int nchunks, const R* twc, const R* tws,
+                 const R* G, hipStream_t st) {
+  constexpr int NC = FftShape<R>::NC, P = FftShape<R>::P;
+  long nlines;
+  if (MODE == kXFwd || MODE == kXInv) nlines = (long)gd.K2 * gd.K3;
+  else if (MODE == kYFwd || MODE == kYInv) nlines = (long)gd.K3 * gd.KX;
+  else nlines = (long)gd.K2 * gd.KX;
+  const long cols = nlines * gd.BG;
+  dim3 grd((unsigned)((cols + NC - 1) / NC), nchunks);
+  const size_t shm = 2 * (size_t)K * NC * sizeof(R);
+  switch (K) {
+#define MBD_CASE(KK)                                                                     \
+    case KK:                                                                             \
+      k_fft<R, KK, NC, P, MODE><<<grd, NC * P, shm, st>>>(grid, gd, twc, tws, G);       \
+      break;
+    MBD_FFT_SIZES(MBD_CASE)
+#undef MBD_CASE
+    default:
+      break;
+  }
+}
+
+}  // namespace
+
+bool fft_supported(int k) {
+  switch (k) {
+#define MBD_CASE(KK) case KK: return true;
+    MBD_FFT_SIZES(MBD_CASE)
+#undef MBD_CASE
+    default:
+      return false;
+  }
+}
+
+// Forward transform of every chunk, convolution with G, inverse transform.
+template <typename R>
+void launch_fft_conv(const Geometry& geo, const SysBuffers& b, int B, int BG, hipStream_t st) {
+  GridDims gd;
+  gd.K1 = geo.K[0];
+  gd.K2 = geo.K[1];
+  gd.K3 = geo.K[2];
+  gd.XS = geo.K[0] + 2;
+  gd.KX = geo.K[0] / 2 + 1;
+  gd.BG = BG;
+  gd.chunk_elems = (size_t)gd.K3 * gd.K2 * gd.XS * BG;
+  const int nchunks = B / BG;
+  R* grid = (R*)b.grid;
+  const R* tw = (const R*)b.tw;
+  const int Ksum = geo.K[0] + geo.K[1] + geo.K[2];
+  const R* c0 = tw;
+  const R* c1 = tw + geo.K[0];
+  const R* c2 = tw + geo.K[0] + geo.K[1];
+  const R* s0 = c0 + Ksum;
+  const R* s1 = c1 + Ksum;
+  const R* s2 = c2 + Ksum;
+  const R* G = (const R*)b.G;
+  launch_pass<R, kXFwd>(geo.K[0], grid, gd, nchunks, c0, s0, G, st);
+  launch_pass<R, kYFwd>(geo.K[1], grid, gd, nchunks, c1, s1, G, st);
+  launch_pass<R, kZConv>(geo.K[2], grid, gd, nchunks, c2, s2, G, st);
+  launch_pass<R, kYInv>(geo.K[1], grid, gd, nchunks, c1, s1, G, st);
+  launch_pass<R, kXInv>(geo.K[0], grid, gd, nchunks, c0, s0, G, st);
+}
+
+template void launch_fft_conv<float>(const Geometry&, const SysBuffers&, int, int, hipStream_t);
+template void launch_fft_conv<double>(const Geometry&, const SysBuffers&, int, int, hipStream_t);
+
+}  // namespace mbd

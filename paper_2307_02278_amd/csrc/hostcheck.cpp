@@ -1,0 +1,42 @@
+// Host-side entry points that run the kernels' scalar math on the CPU.
+#include "../../include/mbd_hostcheck.h"
+
+#include <vector>
+
+#include "mbd_math.h"
+
+extern "C" {
+
+uint64_t mbdh_splitmix(uint64_t seed, uint64_t n) { return mbd::splitmix_at(seed, n); }
+
+int32_t mbdh_bspline(int32_t p, double w, double* th, double* dth) {
+  switch (p) {
+    case 4: mbd::bspline_weights<4>(w, th, dth); return 0;
+    case 6: mbd::bspline_weights<6>(w, th, dth); return 0;
+    case 8: mbd::bspline_weights<8>(w, th, dth); return 0;
+    default: return -1;
+  }
+}
+
+void mbdh_direct_kernel(int32_t prec, double r2, double tau, double inv_s, double damp_d,
+                        double* A, double* B) {
+  if (prec == 1) {
+    float a, b;
+    mbd::direct_kernel<float>((float)r2, (float)tau, (float)inv_s, (float)damp_d, a, b);
+    *A = a;
+    *B = b;
+  } else {
+    mbd::direct_kernel<double>(r2, tau, inv_s, damp_d, *A, *B);
+  }
+}
+
+int32_t mbdh_tridiag_quadrature(const double* a, const double* b, int32_t n, double* q,
+                                double* theta_min) {
+  std::vector<double> d(a, a + n), e(n, 0.0), z(n);
+  for (int k = 0; k + 1 < n; ++k) e[k] = b[k];
+  int ok = 0;
+  *q = mbd::tridiag_sqrt_quadrature(d.data(), e.data(), z.data(), n, theta_min, &ok);
+  return ok;
+}
+
+}  // extern "C"

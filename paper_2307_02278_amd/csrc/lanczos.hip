@@ -1,0 +1,415 @@
+// Lanczos recurrence, Gauss quadrature and energy in double precision
+// (eqs. hutch, dds, recurs2, sl3, sl4, plasmonic2; Algorithms 1 and 2).
+//
+// The Krylov vectors are kept unnormalized: w_0 = v (||v|| = 1), and with
+// nrm_k = ||w_k||, y_k = w_k / nrm_k, l~_k = C w_k,
+//   a_k     = (w_k . l~_k) / nrm_k^2
+//   w_{k+1} = l~_k / nrm_k - a_k w_k / nrm_k - nrm_k w_{k-1} / nrm_{k-1}
+// which is the three-term recurrence b_{k+1} y_{k+1} = l_k - a_k y_k - b_k y_{k-1}
+// with b_{k+1} = nrm_{k+1}; the generalized dipoles of the next step are
+// d = g * w_{k+1} (stored in the SPME precision). Every reduction over atoms is
+// done in a fixed order (per-block partial sums, then one block per RHS).
+#include "common.h"
+#include "mbd_math.h"
+
+namespace mbd {
+
+namespace {
+
+// Block layout for [n][3][B] element-wise kernels: RB lanes over right-hand
+// sides, 256 / RB rows over (atom, component); blockIdx.y selects the RHS group.
+template <int RB>
+struct RowLayout {
+  static constexpr int ROWS = 256 / RB;
+};
+
+__device__ __forceinline__ void block_reduce_rows(double* red, int rb_lanes, int rows) {
+  const int lane = threadIdx.x % rb_lanes;
+  const int row = threadIdx.x / rb_lanes;
+  for (int h = rows / 2; h > 0; h >>= 1) {
+    if (row < h) red[threadIdx.x] += red[threadIdx.x + h * rb_lanes];
+    __syncthreads();
+  }
+  (void)lane;
+}
+
+template <int RB>
+__global__ void __launch_bounds__(256)
+k_probes(int n, int B, int nb, int probe0, uint64_t zs, const int* __restrict__ perm,
+         const double* __restrict__ g, double* __restrict__ w0, double* __restrict__ dtmp,
+         float* __restrict__ df, int use_float) {
+  constexpr int ROWS = 256 / RB;
+  const int b = blockIdx.y * RB + threadIdx.x % RB;
+  const int row0 = blockIdx.x * ROWS + threadIdx.x / RB;
+  if (b >= B) return;
+  const uint64_t D = 3ull * (uint64_t)n;
+  const double inv = 1.0 / sqrt((double)D);
+  for (int row = row0; row < 3 * n; row += gridDim.x * ROWS) {
+    const int s = row / 3, a = row % 3;
+    double v = 0.0;
+    if (b < nb) {
+      const uint64_t l = (uint64_t)(probe0 + b);
+      const uint64_t idx = l * D + 3ull * (uint64_t)perm[s] + (uint64_t)a;
+      const uint64_t h = splitmix_at(zs, idx);
+      v = (h >> 63) ? -inv : inv;
+    }
+    const size_t o = (size_t)row * B + b;
+    w0[o] = v;
+    const double d = g[s] * v;
+    if (use_float) df[o] = (float)d; else dtmp[o] = d;
+  }
+}
+
+template <int RB>
+__global__ void __launch_bounds__(256)
+k_update(int n, int B, int nb, int k, int m, int probe0, const double* __restrict__ lt,
+         const double* __restrict__ wk, const double* __restrict__ wkm1,
+         const double* __restrict__ a, const double* __restrict__ nrm,
+         const int* __restrict__ meff, const double* __restrict__ g, double* __restrict__ wn,
+         double* __restrict__ dtmp, float* __restrict__ df, int use_float, int write_d,
+         double* __restrict__ part) {
+  constexpr int ROWS = 256 / RB;
+  __shared__ double red[256];
+  const int lane = threadIdx.x % RB;
+  const int b = blockIdx.y * RB + lane;
+  const int row0 = blockIdx.x * ROWS + threadIdx.x / RB;
+  double ss = 0.0;
+  if (b < B) {
+    bool live = false;
+    double c_l = 0.0, c_k = 0.0, c_km1 = 0.0;
+    if (b < nb) {
+      const int l = probe0 + b;
+      live = meff[l] > k;  // w_{k+1} is needed only while the probe has not broken down
+      const double nk = nrm[l * m + k];
+      c_l = 1.0 / nk;
+      c_k = a[l * m + k] / nk;
+      c_km1 = (k > 0) ? nk / nrm[l * m + k - 1] : 0.0;
+    }
+    for (int row = row0; row < 3 * n; row += gridDim.x * ROWS) {
+      const size_t o = (size_t)row * B + b;
+      double v = 0.0;
+      if (live) {
+        v = c_l * lt[o] - c_k * wk[o];
+        if (k > 0) v -= c_km1 * wkm1[o];
+      }
+      wn[o] = v;
+      ss += v * v;
+      if (write_d) {
+        const double d = g[row / 3] * v;
+        if (use_float) df[o] = (float)d; else dtmp[o] = d;
+      }
+    }
+  }
+  red[threadIdx.x] = ss;
+  __syncthreads();
+  block_reduce_rows(red, RB, ROWS);
+  if (threadIdx.x < RB && b < B) part[((size_t)blockIdx.x * 4 + 1) * B + b] = red[threadIdx.x];
+}
+
+// Dot products of w with earlier Krylov vectors for re-orthogonalization:
+// coef[b][j] partials of (w . w_j) for j in [j0, j1), written to part slot 2.. via a
+// separate pass per j (the count is small: 2 for LOCAL).
+template <int RB>
+__global__ void __launch_bounds__(256)
+k_dot(int n, int B, const double* __restrict__ x, const double* __restrict__ y,
+      double* __restrict__ part, int slot) {
+  constexpr int ROWS = 256 / RB;
+  __shared__ double red[256];
+  const int lane = threadIdx.x % RB;
+  const int b = blockIdx.y * RB + lane;
+  const int row0 = blockIdx.x * ROWS + threadIdx.x / RB;
+  double ss = 0.0;
+  if (b < B)
+    for (int row = row0; row < 3 * n; row += gridDim.x * ROWS) {
+      const size_t o = (size_t)row * B + b;
+      ss += x[o] * y[o];
+    }
+  red[threadIdx.x] = ss;
+  __syncthreads();
+  block_reduce_rows(red, RB, ROWS);
+  if (threadIdx.x < RB && b < B) part[((size_t)blockIdx.x * 4 + slot) * B + b] = red[threadIdx.x];
+}
+
+// Sum the per-block partials of one slot for each RHS, in a fixed order.
+__global__ void __launch_bounds__(256)
+k_sum_slot(int B, int slot, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int b = blockIdx.x;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < kRedBlocks; k += 256) s += part[((size_t)k * 4 + slot) * B + b];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[b] = red[0];
+}
+
+// w <- w - sum_j c_j w_j with c_j = (w . w_j) / nrm_j^2 for the listed j; then the
+// norm partials and (optionally) the dipoles.
+template <int RB>
+__global__ void __launch_bounds__(256)
+k_orth_apply(int n, int B, int nb, int m, int probe0, const double* __restrict__ W,
+             size_t vstride, int j0, int j1, const double* __restrict__ dots,
+             const double* __restrict__ nrm, const int* __restrict__ meff, int k,
+             const double* __restrict__ g, double* __restrict__ w, double* __restrict__ dtmp,
+             float* __restrict__ df, int use_float, double* __restrict__ part) {
+  constexpr int ROWS = 256 / RB;
+  __shared__ double red[256];
+  const int lane = threadIdx.x % RB;
+  const int b = blockIdx.y * RB + lane;
+  const int row0 = blockIdx.x * ROWS + threadIdx.x / RB;
+  double ss = 0.0;
+  if (b < B) {
+    double c[kMaxSteps < 64 ? kMaxSteps : 64];
+    const int nj = j1 - j0;
+    bool live = false;
+    if (b < nb) {
+      const int l = probe0 + b;
+      live = meff[l] > k;
+      for (int j = 0; j < nj; ++j) {
+        const double nj2 = nrm[l * m + j0 + j];
+        c[j] = dots[(size_t)j * B + b] / (nj2 * nj2);
+      }
+    }
+    for (int row = row0; row < 3 * n; row += gridDim.x * ROWS) {
+      const size_t o = (size_t)row * B + b;
+      double v = w[o];
+      if (live)
+        for (int j = 0; j < nj; ++j) v -= c[j] * W[(size_t)(j0 + j) * vstride + o];
+      else
+        v = 0.0;
+      w[o] = v;
+      ss += v * v;
+      const double d = g[row / 3] * v;
+      if (use_float) df[o] = (float)d; else dtmp[o] = d;
+    }
+  }
+  red[threadIdx.x] = ss;
+  __syncthreads();
+  block_reduce_rows(red, RB, ROWS);
+  if (threadIdx.x < RB && b < B) part[((size_t)blockIdx.x * 4 + 1) * B + b] = red[threadIdx.x];
+}
+
+// a_k from the epilogue partials (slot 0).
+__global__ void k_finish_a(int B, int nb, int k, int m, int probe0, const double* __restrict__ sums,
+                           const double* __restrict__ nrm, double* __restrict__ a,
+                           const int* __restrict__ meff, uint32_t* __restrict__ status) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const int l = probe0 + b;
+  if (meff[l] <= k) return;
+  const double nk = nrm[l * m + k];
+  const double v = sums[b] / (nk * nk);
+  a[l * m + k] = v;
+  if (!isfinite(v)) atomicOr(status, kErrNonfinite);
+}
+
+// nrm_{k+1} from the update partials (slot 1); breakdown truncates the tridiagonal.
+__global__ void k_finish_norm(int B, int nb, int k, int m, int probe0,
+                              const double* __restrict__ sums, double* __restrict__ nrm,
+                              const double* __restrict__ a, int* __restrict__ meff,
+                              uint32_t* __restrict__ status) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const int l = probe0 + b;
+  if (meff[l] <= k) return;
+  const double v = sqrt(sums[b]);
+  nrm[l * m + k + 1] = v;
+  const double scale = fmax(fabs(a[l * m + k]), nrm[l * m + k]);
+  if (!isfinite(v)) atomicOr(status, kErrNonfinite);
+  if (!(v > 1e-12 * scale)) meff[l] = k + 1;
+}
+
+__global__ void k_init_probe_scalars(int nb, int m, int probe0, double* __restrict__ nrm,
+                                     double* __restrict__ a, int* __restrict__ meff) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const int l = probe0 + b;
+  for (int k = 0; k < m; ++k) {
+    nrm[l * m + k] = 0.0;
+    a[l * m + k] = 0.0;
+  }
+  nrm[l * m] = 1.0;
+  meff[l] = m;
+}
+
+// Gauss quadrature per probe from its tridiagonal (implicit QR, first-row tracking).
+__global__ void k_tridiag(int nb, int m, int probe0, const double* __restrict__ a,
+                          const double* __restrict__ nrm, const int* __restrict__ meff,
+                          double* __restrict__ q, uint32_t* __restrict__ status) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const int l = probe0 + b;
+  double d[kMaxSteps], e[kMaxSteps], z[kMaxSteps];
+  const int n = meff[l];
+  for (int k = 0; k < n; ++k) {
+    d[k] = a[l * m + k];
+    e[k] = (k + 1 < n) ? nrm[l * m + k + 1] : 0.0;
+  }
+  double tmin;
+  int ok;
+  const double v = tridiag_sqrt_quadrature(d, e, z, n, &tmin, &ok);
+  q[l] = v;
+  if (!ok) atomicOr(status, kErrNoConverge);
+  if (!(tmin > 0.0)) atomicOr(status, kErrNotPosdef);
+  if (!isfinite(v)) atomicOr(status, kErrNonfinite);
+}
+
+// E = 1/2 (3N / R) sum_l Q_l - 3/2 sum_i omega_i, summed in probe order.
+__global__ void k_energy(int n, int R, const double* __restrict__ q,
+                         const double* __restrict__ g, const double* __restrict__ om2,
+                         double* __restrict__ out, uint32_t* __restrict__ status) {
+  __shared__ double red[256];
+  double so = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) so += sqrt(om2[i]);
+  red[threadIdx.x] = so;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double sq = 0.0;
+    for (int l = 0; l < R; ++l) sq += q[l];
+    const double E = 0.5 * (3.0 * n / R) * sq - 1.5 * red[0];
+    out[0] = E;
+    if (!isfinite(E)) atomicOr(status, kErrNonfinite);
+  }
+  (void)g;
+}
+
+// Caller layout [nrhs][N][3] (caller atom order) <-> internal [n][3][B] (sorted).
+__global__ void k_pack(int n, int nrhs, int B, const int* __restrict__ perm,
+                       const double* __restrict__ v, const double* __restrict__ g,
+                       double* __restrict__ w, double* __restrict__ dtmp,
+                       float* __restrict__ df, int use_float) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)3 * n * B) return;
+  const int b = (int)(t % B);
+  const long row = t / B;
+  const int s = (int)(row / 3), a = (int)(row % 3);
+  const double x = (b < nrhs) ? v[((size_t)b * n + perm[s]) * 3 + a] : 0.0;
+  w[t] = x;
+  const double d = g[s] * x;
+  if (use_float) df[t] = (float)d; else dtmp[t] = d;
+}
+
+__global__ void k_unpack(int n, int nrhs, int B, const int* __restrict__ perm,
+                         const double* __restrict__ lt, double* __restrict__ out) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)3 * n * B) return;
+  const int b = (int)(t % B);
+  if (b >= nrhs) return;
+  const long row = t / B;
+  const int s = (int)(row / 3), a = (int)(row % 3);
+  out[((size_t)b * n + perm[s]) * 3 + a] = lt[t];
+}
+
+inline int rb_for(int B) { return B >= 64 ? 64 : B; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launch wrappers
+// ---------------------------------------------------------------------------
+#define MBD_RB_SWITCH(RBV, CALL)         \
+  switch (RBV) {                         \
+    case 1: { constexpr int RB = 1; CALL; } break;   \
+    case 2: { constexpr int RB = 2; CALL; } break;   \
+    case 4: { constexpr int RB = 4; CALL; } break;   \
+    case 8: { constexpr int RB = 8; CALL; } break;   \
+    case 16: { constexpr int RB = 16; CALL; } break; \
+    case 32: { constexpr int RB = 32; CALL; } break; \
+    default: { constexpr int RB = 64; CALL; } break; \
+  }
+
+void launch_probes(const Geometry& geo, const SysBuffers& b, int B, int nb, int probe0,
+                   uint64_t seed, int system, bool use_float, hipStream_t st) {
+  const uint64_t zs = splitmix_at(seed, (uint64_t)system);
+  const int rb = rb_for(B);
+  dim3 grd(kRedBlocks, (B + rb - 1) / rb);
+  MBD_RB_SWITCH(rb, (k_probes<RB><<<grd, 256, 0, st>>>(geo.n, B, nb, probe0, zs, b.perm, b.g,
+                                                       b.W, (double*)b.dv, (float*)b.dv,
+                                                       use_float ? 1 : 0)));
+}
+
+void launch_init_scalars(const SysBuffers& b, int nb, int m, int probe0, hipStream_t st) {
+  k_init_probe_scalars<<<(nb + 63) / 64, 64, 0, st>>>(nb, m, probe0, b.b, b.a, b.meff);
+}
+
+void launch_update(const Geometry& geo, const SysBuffers& b, int B, int nb, int k, int m,
+                   int probe0, bool use_float, bool write_d, hipStream_t st) {
+  const size_t vs = (size_t)geo.n * 3 * B;
+  const int rb = rb_for(B);
+  dim3 grd(kRedBlocks, (B + rb - 1) / rb);
+  const double* wk = b.W + (size_t)k * vs;
+  const double* wkm1 = k > 0 ? b.W + (size_t)(k - 1) * vs : b.W;
+  double* wn = b.W + (size_t)(k + 1) * vs;
+  MBD_RB_SWITCH(rb, (k_update<RB><<<grd, 256, 0, st>>>(
+                         geo.n, B, nb, k, m, probe0, b.Lt, wk, wkm1, b.a, b.b, b.meff, b.g, wn,
+                         (double*)b.dv, (float*)b.dv, use_float ? 1 : 0, write_d ? 1 : 0,
+                         b.part)));
+}
+
+// Re-orthogonalize w_{k+1} against w_j for j in [j0, k] (classical Gram-Schmidt,
+// in chunks of at most 64 earlier vectors).
+void launch_reorth(const Geometry& geo, const SysBuffers& b, int B, int nb, int k, int m,
+                   int probe0, int j0, bool use_float, hipStream_t st) {
+  const size_t vs = (size_t)geo.n * 3 * B;
+  const int rb = rb_for(B);
+  dim3 grd(kRedBlocks, (B + rb - 1) / rb);
+  double* w = b.W + (size_t)(k + 1) * vs;
+  for (int c0 = j0; c0 <= k; c0 += 64) {
+    const int c1 = (k + 1 < c0 + 64) ? k + 1 : c0 + 64;
+    for (int j = c0; j < c1; ++j) {
+      MBD_RB_SWITCH(rb, (k_dot<RB><<<grd, 256, 0, st>>>(geo.n, B, w, b.W + (size_t)j * vs,
+                                                        b.part, 2)));
+      k_sum_slot<<<B, 256, 0, st>>>(B, 2, b.part, b.coef + (size_t)(j - c0) * B);
+    }
+    MBD_RB_SWITCH(rb, (k_orth_apply<RB><<<grd, 256, 0, st>>>(
+                           geo.n, B, nb, m, probe0, b.W, vs, c0, c1, b.coef, b.b, b.meff, k,
+                           b.g, w, (double*)b.dv, (float*)b.dv, use_float ? 1 : 0, b.part)));
+  }
+}
+
+void launch_finish_a(const SysBuffers& b, int B, int nb, int k, int m, int probe0,
+                     uint32_t* status, hipStream_t st) {
+  k_sum_slot<<<B, 256, 0, st>>>(B, 0, b.part, b.coef);
+  k_finish_a<<<(nb + 63) / 64, 64, 0, st>>>(B, nb, k, m, probe0, b.coef, b.b, b.a, b.meff,
+                                            status);
+}
+
+void launch_finish_norm(const SysBuffers& b, int B, int nb, int k, int m, int probe0,
+                        uint32_t* status, hipStream_t st) {
+  k_sum_slot<<<B, 256, 0, st>>>(B, 1, b.part, b.coef);
+  k_finish_norm<<<(nb + 63) / 64, 64, 0, st>>>(B, nb, k, m, probe0, b.coef, b.b, b.a, b.meff,
+                                               status);
+}
+
+void launch_tridiag(const SysBuffers& b, int nb, int m, int probe0, uint32_t* status,
+                    hipStream_t st) {
+  k_tridiag<<<(nb + 31) / 32, 32, 0, st>>>(nb, m, probe0, b.a, b.b, b.meff, b.q, status);
+}
+
+void launch_energy(const Geometry& geo, const SysBuffers& b, int R, double* energy_out,
+                   uint32_t* status, hipStream_t st) {
+  k_energy<<<1, 256, 0, st>>>(geo.n, R, b.q, b.g, b.om2, energy_out, status);
+}
+
+void launch_pack(const Geometry& geo, const SysBuffers& b, const double* v, int nrhs, int B,
+                 bool use_float, hipStream_t st) {
+  const long tot = (long)3 * geo.n * B;
+  k_pack<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(geo.n, nrhs, B, b.perm, v, b.g, b.W,
+                                                         (double*)b.dv, (float*)b.dv,
+                                                         use_float ? 1 : 0);
+}
+
+void launch_unpack(const Geometry& geo, const SysBuffers& b, double* out, int nrhs, int B,
+                   hipStream_t st) {
+  const long tot = (long)3 * geo.n * B;
+  k_unpack<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(geo.n, nrhs, B, b.perm, b.Lt, out);
+}
+
+}  // namespace mbd

@@ -1,0 +1,254 @@
+// Position-dependent setup (once per energy evaluation): wrap positions into the
+// cell, sort atoms by cell-list cell, cell-local coordinates for the pair kernel,
+// B-spline tables at the scaled fractional coordinates u_a = K_a R_a / L_a
+// (eq. scaledfractional, formed in double precision), and the per-tile atom lists
+// of the spread kernel.
+#include "common.h"
+#include "mbd_math.h"
+
+namespace mbd {
+
+namespace {
+
+__global__ void k_wrap_count(int n, const double* __restrict__ pos, double L0, double L1,
+                             double L2, int nc0, int nc1, int nc2, double h0, double h1,
+                             double h2, double* __restrict__ wpos, int* __restrict__ cell_of,
+                             int* __restrict__ count) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double L[3] = {L0, L1, L2};
+  const double h[3] = {h0, h1, h2};
+  const int nc[3] = {nc0, nc1, nc2};
+  int c[3];
+  for (int a = 0; a < 3; ++a) {
+    double x = pos[3 * i + a];
+    x -= L[a] * floor(x / L[a]);
+    if (x >= L[a]) x -= L[a];
+    if (x < 0.0) x = 0.0;
+    wpos[3 * i + a] = x;
+    int ci = (int)(x / h[a]);
+    c[a] = ci >= nc[a] ? nc[a] - 1 : ci;
+  }
+  int cell = (c[2] * nc[1] + c[1]) * nc[0] + c[0];
+  cell_of[i] = cell;
+  atomicAdd(&count[cell], 1);
+}
+
+// Exclusive scan of count[0..m) into start[0..m]; one block.
+__global__ void k_scan(int m, const int* __restrict__ count, int* __restrict__ start) {
+  __shared__ int chunk_sums[1024];
+  const int T = blockDim.x;
+  const int per = (m + T - 1) / T;
+  const int lo = threadIdx.x * per;
+  const int hi = min(m, lo + per);
+  int s = 0;
+  for (int i = lo; i < hi; ++i) s += count[i];
+  chunk_sums[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int t = 0; t < T; ++t) {
+      int v = chunk_sums[t];
+      chunk_sums[t] = acc;
+      acc += v;
+    }
+    start[m] = acc;
+  }
+  __syncthreads();
+  int acc = chunk_sums[threadIdx.x];
+  for (int i = lo; i < hi; ++i) {
+    start[i] = acc;
+    acc += count[i];
+  }
+}
+
+__global__ void k_scatter(int n, const int* __restrict__ cell_of, const int* __restrict__ start,
+                          int* __restrict__ cursor, int* __restrict__ perm) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int c = cell_of[i];
+  int slot = atomicAdd(&cursor[c], 1);
+  perm[start[c] + slot] = i;
+}
+
+// Make the order inside each cell deterministic: ascending caller index.
+__global__ void k_sort_cells(int ncell, const int* __restrict__ start, int* __restrict__ perm) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  int lo = start[c], hi = start[c + 1];
+  for (int i = lo + 1; i < hi; ++i) {
+    int v = perm[i];
+    int j = i - 1;
+    while (j >= lo && perm[j] > v) {
+      perm[j + 1] = perm[j];
+      --j;
+    }
+    perm[j + 1] = v;
+  }
+}
+
+template <typename R, int P>
+__global__ void k_sorted_tables(Geometry geo, const int* __restrict__ perm,
+                                const double* __restrict__ wpos,
+                                const double* __restrict__ alpha, const double* __restrict__ omega,
+                                const double* __restrict__ rvdw, R* __restrict__ loc,
+                                double* __restrict__ g, double* __restrict__ om2,
+                                int* __restrict__ base, R* __restrict__ th, R* __restrict__ dth,
+                                int* __restrict__ tile_count, int* __restrict__ scell) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= geo.n) return;
+  const int i = perm[s];
+  double x[3];
+  int c[3];
+  for (int a = 0; a < 3; ++a) {
+    x[a] = wpos[3 * i + a];
+    int ci = (int)(x[a] / geo.hc[a]);
+    c[a] = ci >= geo.nc[a] ? geo.nc[a] - 1 : ci;
+  }
+  for (int a = 0; a < 3; ++a) loc[4 * s + a] = (R)(x[a] - c[a] * geo.hc[a]);
+  scell[s] = (c[2] * geo.nc[1] + c[1]) * geo.nc[0] + c[0];
+  loc[4 * s + 3] = (R)(geo.beta * rvdw[i]);
+  g[s] = omega[i] * sqrt(alpha[i]);
+  om2[s] = omega[i] * omega[i];
+  for (int a = 0; a < 3; ++a) {
+    const double u = geo.K[a] * x[a] / geo.L[a];
+    double fl = floor(u);
+    double w = u - fl;
+    int b0 = (int)fl;
+    if (w >= 1.0) { w = 0.0; b0 += 1; }
+    b0 %= geo.K[a];
+    if (b0 < 0) b0 += geo.K[a];
+    base[3 * s + a] = b0;
+    double t[P], dt[P];
+    bspline_weights<P>(w, t, dt);
+    const double scale = geo.K[a] / geo.L[a];
+    for (int k = 0; k < P; ++k) {
+      th[(s * 3 + a) * P + k] = (R)t[k];
+      dth[(s * 3 + a) * P + k] = (R)(dt[k] * scale);
+    }
+  }
+  // tiles touched by the stencil k = base - t, t = 0..P-1 (mod K), per axis
+  int tl[3][3], nt[3];
+  for (int a = 0; a < 3; ++a) {
+    nt[a] = 0;
+    for (int k = 0; k < P; ++k) {
+      int kk = base[3 * s + a] - k;
+      if (kk < 0) kk += geo.K[a];
+      int tt = kk / kSpreadTile;
+      bool seen = false;
+      for (int q = 0; q < nt[a]; ++q) seen |= (tl[a][q] == tt);
+      if (!seen) tl[a][nt[a]++] = tt;
+    }
+  }
+  for (int z = 0; z < nt[2]; ++z)
+    for (int y = 0; y < nt[1]; ++y)
+      for (int xx = 0; xx < nt[0]; ++xx) {
+        int tile = (tl[2][z] * geo.tiles[1] + tl[1][y]) * geo.tiles[0] + tl[0][xx];
+        atomicAdd(&tile_count[tile], 1);
+      }
+}
+
+template <int P>
+__global__ void k_tile_fill(Geometry geo, const int* __restrict__ base,
+                            const int* __restrict__ tile_start, int* __restrict__ cursor,
+                            int* __restrict__ tile_atoms) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= geo.n) return;
+  int tl[3][3], nt[3];
+  for (int a = 0; a < 3; ++a) {
+    nt[a] = 0;
+    for (int k = 0; k < P; ++k) {
+      int kk = base[3 * s + a] - k;
+      if (kk < 0) kk += geo.K[a];
+      int tt = kk / kSpreadTile;
+      bool seen = false;
+      for (int q = 0; q < nt[a]; ++q) seen |= (tl[a][q] == tt);
+      if (!seen) tl[a][nt[a]++] = tt;
+    }
+  }
+  for (int z = 0; z < nt[2]; ++z)
+    for (int y = 0; y < nt[1]; ++y)
+      for (int xx = 0; xx < nt[0]; ++xx) {
+        int tile = (tl[2][z] * geo.tiles[1] + tl[1][y]) * geo.tiles[0] + tl[0][xx];
+        int slot = atomicAdd(&cursor[tile], 1);
+        tile_atoms[tile_start[tile] + slot] = s;
+      }
+}
+
+// Deterministic order inside each tile's list.
+__global__ void k_sort_tiles(int ntiles, const int* __restrict__ start, int* __restrict__ list) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ntiles) return;
+  int lo = start[c], hi = start[c + 1];
+  for (int i = lo + 1; i < hi; ++i) {
+    int v = list[i];
+    int j = i - 1;
+    while (j >= lo && list[j] > v) {
+      list[j + 1] = list[j];
+      --j;
+    }
+    list[j + 1] = v;
+  }
+}
+
+inline int blocks_for(int n, int t) { return (n + t - 1) / t; }
+
+__global__ void k_fill_int(int* __restrict__ p, int v, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+// Kernel-based clear (kept out of hipMemsetAsync so that the sequence can be captured).
+void fill_int(int* p, int v, int n, hipStream_t st) {
+  k_fill_int<<<blocks_for(n, 256), 256, 0, st>>>(p, v, n);
+}
+
+template <typename R>
+void launch_setup(const Geometry& g, SysBuffers& b, const double* pos, const double* alpha,
+                  const double* omega, const double* rvdw, hipStream_t st) {
+  const int ncell = g.nc[0] * g.nc[1] * g.nc[2];
+  const int ntiles = g.tiles[0] * g.tiles[1] * g.tiles[2];
+  fill_int(b.cell_cursor, 0, ncell, st);
+  k_wrap_count<<<blocks_for(g.n, 256), 256, 0, st>>>(
+      g.n, pos, g.L[0], g.L[1], g.L[2], g.nc[0], g.nc[1], g.nc[2], g.hc[0], g.hc[1], g.hc[2],
+      b.wpos, b.cell_of, b.cell_cursor);
+  k_scan<<<1, 1024, 0, st>>>(ncell, b.cell_cursor, b.cell_start);
+  fill_int(b.cell_cursor, 0, ncell, st);
+  k_scatter<<<blocks_for(g.n, 256), 256, 0, st>>>(g.n, b.cell_of, b.cell_start, b.cell_cursor,
+                                                   b.perm);
+  k_sort_cells<<<blocks_for(ncell, 128), 128, 0, st>>>(ncell, b.cell_start, b.perm);
+  fill_int(b.tile_count, 0, ntiles + 1, st);
+#define MBD_TABLES(PP)                                                                        \
+  k_sorted_tables<R, PP><<<blocks_for(g.n, 128), 128, 0, st>>>(                               \
+      g, b.perm, b.wpos, alpha, omega, rvdw, (R*)b.loc, b.g, b.om2, b.base, (R*)b.th,        \
+      (R*)b.dth, b.tile_count, b.scell)
+  switch (g.p) {
+    case 4: MBD_TABLES(4); break;
+    case 6: MBD_TABLES(6); break;
+    case 8: MBD_TABLES(8); break;
+  }
+#undef MBD_TABLES
+  k_scan<<<1, 1024, 0, st>>>(ntiles, b.tile_count, b.tile_start);
+  fill_int(b.tile_count, 0, ntiles + 1, st);
+  switch (g.p) {
+    case 4: k_tile_fill<4><<<blocks_for(g.n, 256), 256, 0, st>>>(g, b.base, b.tile_start,
+                                                                  b.tile_count, b.tile_atoms);
+      break;
+    case 6: k_tile_fill<6><<<blocks_for(g.n, 256), 256, 0, st>>>(g, b.base, b.tile_start,
+                                                                  b.tile_count, b.tile_atoms);
+      break;
+    case 8: k_tile_fill<8><<<blocks_for(g.n, 256), 256, 0, st>>>(g, b.base, b.tile_start,
+                                                                  b.tile_count, b.tile_atoms);
+      break;
+  }
+  k_sort_tiles<<<blocks_for(ntiles, 128), 128, 0, st>>>(ntiles, b.tile_start, b.tile_atoms);
+}
+
+template void launch_setup<float>(const Geometry&, SysBuffers&, const double*, const double*,
+                                  const double*, const double*, hipStream_t);
+template void launch_setup<double>(const Geometry&, SysBuffers&, const double*, const double*,
+                                   const double*, const double*, hipStream_t);
+
+}  // namespace mbd

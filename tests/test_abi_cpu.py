@@ -1,0 +1,210 @@
+"""CPU-side checks of the C ABI library: it loads, exports every declared symbol,
+rejects bad arguments before touching a device, and its scalar math (compiled for
+the host from the kernels' own source) agrees with the oracle."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import lanczos as olz
+from oracle import probes as opr
+from oracle import spme as osp
+from oracle import tensors as otz
+from paper_2307_02278_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+pytestmark = pytest.mark.skipif(not os.path.exists(L.LIB_PATH),
+                                reason="libmbd.so not built (run __graft_entry__.build())")
+
+
+def _declared(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mbdh?_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(L.LIB_PATH)
+    names = _declared("mbd.h")
+    assert "mbd_plan_create" in names and "mbd_execute" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    bound = {s[0] for s in L.SIGNATURES}
+    assert set(names) == bound
+
+
+def test_hostcheck_exports_every_declared_symbol():
+    lib = C.CDLL(L.HOSTCHECK_PATH)
+    names = _declared("mbd_hostcheck.h")
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == {s[0] for s in L.HOSTCHECK_SIGNATURES}
+
+
+def test_status_strings_and_grid_support():
+    lib = L.lib()
+    assert lib.mbd_status_string(0) == b"ok"
+    assert lib.mbd_status_string(L.MBD_E_GRID) == b"unsupported grid"
+    for k in (8, 16, 18, 20, 24, 30, 48, 80, 96, 128):
+        assert lib.mbd_grid_supported(k) == 1
+    for k in (7, 14, 22, 130, 256):
+        assert lib.mbd_grid_supported(k) == 0
+
+
+def _args(n=4, cell=(20.0, 20.0, 20.0)):
+    s = L.MbdSystem()
+    s.n_atoms = n
+    fake = 0x1000  # never dereferenced: validation fails (or no device) first
+    s.pos = s.alpha = s.omega = s.r_vdw = fake
+    for i in range(9):
+        s.cell[i] = 0.0
+    for a in range(3):
+        s.cell[4 * a] = cell[a]
+    p = L.MbdParams()
+    p.damp_beta, p.damp_d, p.ewald_tau, p.real_cutoff, p.damp_tol = 0.83, 6.0, 0.2, 12.0, 0.0
+    for a in range(3):
+        p.grid[a] = 16
+    p.spline_order, p.n_probes, p.n_steps, p.block = 6, 4, 10, 4
+    p.seed, p.precision, p.reorth, p.want_forces, p.deterministic = 1, 0, 0, 0, 0
+    return s, p
+
+
+def _create(s, p, nsys=1):
+    h = C.c_void_p()
+    arr = (L.MbdSystem * nsys)(*([s] * nsys))
+    code = L.lib().mbd_plan_create(C.byref(h), arr, nsys, C.byref(p), None)
+    return code, h
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda s, p: setattr(p, "damp_beta", -1.0), L.MBD_E_ARG),
+    (lambda s, p: setattr(p, "damp_d", 0.0), L.MBD_E_ARG),
+    (lambda s, p: setattr(p, "real_cutoff", float("nan")), L.MBD_E_ARG),
+    (lambda s, p: setattr(p, "spline_order", 5), L.MBD_E_ARG),
+    (lambda s, p: setattr(p, "n_probes", 0), L.MBD_E_ARG),
+    (lambda s, p: setattr(p, "n_steps", 0), L.MBD_E_ARG),
+    (lambda s, p: setattr(p, "n_steps", 100000), L.MBD_E_ARG),
+    (lambda s, p: setattr(p, "block", 3), L.MBD_E_ARG),
+    (lambda s, p: setattr(p, "precision", 7), L.MBD_E_ARG),
+    (lambda s, p: setattr(p, "reorth", 9), L.MBD_E_ARG),
+    (lambda s, p: setattr(p, "want_forces", 1), L.MBD_E_ARG),
+    (lambda s, p: setattr(s, "n_atoms", 0), L.MBD_E_ARG),
+    (lambda s, p: setattr(s, "pos", None), L.MBD_E_ARG),
+    (lambda s, p: s.cell.__setitem__(1, 0.5), L.MBD_E_CELL),
+    (lambda s, p: s.cell.__setitem__(0, -3.0), L.MBD_E_CELL),
+    (lambda s, p: p.grid.__setitem__(0, 14), L.MBD_E_GRID),
+    (lambda s, p: p.grid.__setitem__(1, 10), L.MBD_E_GRID),  # supported but < 2p
+])
+def test_invalid_arguments_fail_before_device_work(mutate, code):
+    s, p = _args()
+    mutate(s, p)
+    got, h = _create(s, p)
+    assert got == code
+    assert not h.value
+    assert L.lib().mbd_last_error()
+
+
+def test_valid_arguments_without_gpu_report_no_device():
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    s, p = _args()
+    got, h = _create(s, p)
+    assert got == L.MBD_E_NODEVICE
+    assert not h.value
+
+
+def test_null_handles_are_rejected():
+    lib = L.lib()
+    assert lib.mbd_execute(None, None, None) == L.MBD_E_ARG
+    assert lib.mbd_matvec(None, 0, None, None, 1, 15) == L.MBD_E_ARG
+    assert lib.mbd_plan_destroy(None) == L.MBD_OK
+
+
+# --- kernel scalar math on the host vs the oracle ---------------------------------
+
+def test_hostcheck_splitmix_matches_oracle():
+    h = L.hostcheck()
+    for seed, n in [(0, 0), (12345, 17), (2 ** 63 + 5, 10 ** 9)]:
+        assert h.mbdh_splitmix(seed, n) == int(opr.splitmix64(seed, [n])[0])
+
+
+@pytest.mark.parametrize("p", [4, 6, 8])
+def test_hostcheck_bspline_matches_oracle(p):
+    h = L.hostcheck()
+    th = (C.c_double * p)()
+    dth = (C.c_double * p)()
+    for w in (0.0, 0.123, 0.5, 0.999999):
+        assert h.mbdh_bspline(p, w, th, dth) == 0
+        x = torch.tensor([w + t for t in range(p)], dtype=torch.float64)
+        assert np.allclose(list(th), osp.bspline(p, x).numpy(), atol=1e-15)
+        assert np.allclose(list(dth), osp.bspline_deriv(p, x).numpy(), atol=1e-14)
+    assert h.mbdh_bspline(5, 0.1, th, dth) == -1
+
+
+def _oracle_direct(r, tau, S, d):
+    A, B = otz.radial_direct(torch.tensor([r], dtype=torch.float64), tau,
+                             torch.tensor([S], dtype=torch.float64), d)
+    return float(A[0]), float(B[0])
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-13), (1, 2e-6)])
+def test_hostcheck_direct_kernel_matches_oracle(prec, tol):
+    h = L.hostcheck()
+    A = C.c_double()
+    B = C.c_double()
+    tau, d = 0.2223, 6.0
+    for S in (5.15, 5.98):
+        for r in np.concatenate([np.linspace(1.6, 4.0, 13), np.linspace(4.0, 25.0, 40)]):
+            h.mbdh_direct_kernel(prec, r * r, tau, 1.0 / S, d, C.byref(A), C.byref(B))
+            Ao, Bo = _oracle_direct(r, tau, S, d)
+            # compare the eigenvalues A and A - B r^2 of the 3x3 tensor; where the erfc part
+            # and the damping tail cancel, the floor is 1e-3 of the bare tensor 1/r^3
+            scale = max(abs(Ao), abs(Ao - Bo * r * r)) + (1e-3 / r ** 3 if prec == 1 else 0.0)
+            assert abs(A.value - Ao) <= tol * scale, (r, A.value, Ao)
+            assert abs((A.value - B.value * r * r) - (Ao - Bo * r * r)) <= tol * scale, r
+
+
+def test_hostcheck_direct_kernel_short_range_series():
+    """The single-precision short-range path (Taylor series of the erf part)."""
+    h = L.hostcheck()
+    A = C.c_double()
+    B = C.c_double()
+    tau, d, S = 0.35, 6.0, 5.5
+    for r in (0.6, 1.0, 1.4):
+        h.mbdh_direct_kernel(1, r * r, tau, 1.0 / S, d, C.byref(A), C.byref(B))
+        Ao, Bo = _oracle_direct(r, tau, S, d)
+        scale = max(abs(Ao), abs(Ao - Bo * r * r))
+        assert abs(A.value - Ao) <= 2e-6 * scale
+        assert abs(B.value - Bo) * r * r <= 2e-6 * scale
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 17, 50])
+def test_hostcheck_tridiagonal_quadrature_matches_eigh(n):
+    h = L.hostcheck()
+    rng = np.random.default_rng(n)
+    a = rng.uniform(0.2, 0.6, n)
+    b = rng.uniform(0.01, 0.1, max(n - 1, 0))
+    q = C.c_double()
+    tmin = C.c_double()
+    ok = h.mbdh_tridiag_quadrature((C.c_double * n)(*a), (C.c_double * max(n - 1, 1))(*b), n,
+                                   C.byref(q), C.byref(tmin))
+    assert ok == 1
+    qo, theta, _ = olz.quadrature(torch.tensor(a), torch.tensor(b))
+    assert q.value == pytest.approx(float(qo), rel=1e-13)
+    assert tmin.value == pytest.approx(float(theta.min()), rel=1e-12)
+
+
+def test_hostcheck_tridiagonal_flags_indefinite():
+    h = L.hostcheck()
+    a = [0.5, -0.3, 0.4]
+    b = [0.1, 0.2]
+    q = C.c_double()
+    tmin = C.c_double()
+    h.mbdh_tridiag_quadrature((C.c_double * 3)(*a), (C.c_double * 2)(*b), 3, C.byref(q),
+                              C.byref(tmin))
+    assert tmin.value < 0
