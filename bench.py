@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Benchmark of the SPME stochastic-Lanczos MBD hot path on one MI355X.
+
+One step = one full E_MBD evaluation of the 24,000-atom water box (8000 rigid
+molecules at 1 g/cm^3, 62.09 A cube): device setup at the step's positions,
+128 Rademacher probes as one block of right-hand sides, 50 Lanczos steps
+(6400 probe-vector matvecs through the pair kernel and SPME on a 96^3 grid,
+order-6 B-splines, 9 A real-space cutoff), the tridiagonal quadrature and the
+energy sum. SPME and the pair kernel run in float32, the Lanczos recurrence,
+quadrature and energy in float64 ("mixed").
+
+Prints one JSON line on stdout; progress goes to stderr.
+  metric  probe-vector SPME matvecs per second (batched, mixed precision)
+  extra   plain one-vector float64 rate on the same GPU, the speedup, per-stage
+          times, the roofline of the dominant kernel and the CPU oracle rate.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 FMA lanes x 2 flop x 2.4 GHz (no packed FP32)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stage_bytes(stage, K, N, B):
+    """Algorithmic HBM bytes of one launch of a grid stage (B right-hand sides, float32)."""
+    K1, K2, K3 = K
+    real = 4.0 * K1 * K2 * K3
+    cplx = 8.0 * K2 * K3 * (K1 // 2 + 1)
+    per = {
+        "spread": real + 12.0 * N,                  # write the real grid, read the dipoles
+        "fft_x": real + cplx,                       # read real lines, write half spectrum
+        "fft_y": 2 * cplx,
+        "fft_z_conv": 2 * cplx,
+        "ifft_y": 2 * cplx,
+        "ifft_x": cplx + real,
+        "gather": real + 12.0 * N + 48.0 * N,       # read phi, E_dir, w; write l
+    }.get(stage)
+    return None if per is None else per * B
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--plain-probes", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(probes would shard across GPUs with one final all-reduce).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2307_02278_amd as P
+
+    wl = synth.workload("batched24k")
+    s = wl.systems[0]
+    A = synth.ANGSTROM_BOHR
+    K = tuple(wl.grid) * 3 if len(wl.grid) == 1 else tuple(wl.grid)
+    R, m, B = wl.n_probes, wl.n_steps, wl.block
+    log(f"workload: water N={s.n} L={s.cell[0, 0] / A:.2f} A K={K} R={R} m={m} B={B}")
+    ds = P.DeviceSystem(s.pos, s.cell, s.alpha, s.omega, s.rvdw)
+    prm = P.Params(real_cutoff=wl.real_cutoff_angstrom * A, grid=K, n_probes=R, n_steps=m,
+                   block=B, precision=P.PREC_MIXED, seed=wl.probe_seed)
+    plan = P.Plan([ds], prm)
+    info = plan.info(0)
+    n_pairs = int(info.n_pairs)
+    log(f"tau={info.tau:.6f}/bohr r_pair={info.r_pair / A:.3f} A cells={list(info.cells)} "
+        f"pairs={n_pairs} workspace={info.workspace_bytes / 2**30:.2f} GiB")
+    pos = torch.as_tensor(s.pos, dtype=torch.float64, device="cuda")
+
+    def step():
+        plan.set_positions(pos)
+        return plan.execute()
+
+    for w in range(args.warmup):
+        e = step()
+        torch.cuda.synchronize()
+        plan.check()
+        log(f"warmup {w}: E = {float(e[0]):.10e} Ha")
+    plan.stage_times()
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        e = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.set_timing(False)
+    plan.check()
+    stages = plan.stage_times()
+    dt = t1 - t0
+    energy = float(e[0])
+    ms_per_step = 1000.0 * dt / args.steps
+    value = R * m * args.steps / dt
+    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.1f} matvecs/s, "
+        f"E = {energy:.10e}")
+
+    # Per-stage averages and the dominant kernel's roofline.
+    stage_ms = {k: v[0] / args.steps for k, v in stages.items() if v[1] > 0}
+    kernel_stages = {k: v for k, v in stages.items()
+                     if v[1] > 0 and k not in ("lanczos", "setup")}
+    dom = max(kernel_stages, key=lambda k: kernel_stages[k][0])
+    dom_ms_avg = kernel_stages[dom][0] / kernel_stages[dom][1]
+    if dom == "pair":
+        flops = 18.0 * n_pairs * B
+        achieved = flops / (dom_ms_avg * 1e-3) / 1e12
+        roof = {"kernel": "pair", "bound": "alu", "achieved": round(achieved, 3),
+                "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_VALU_PEAK_TFLOPS, 4), "traffic": None,
+                "avg_launch_ms": round(dom_ms_avg, 4),
+                "algorithmic_per_launch": f"18 flop x {n_pairs} pairs x {B} rhs"}
+    else:
+        by = stage_bytes(dom, K, s.n, B)
+        achieved = by / (dom_ms_avg * 1e-3) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "avg_launch_ms": round(dom_ms_avg, 4),
+                "algorithmic_per_launch": f"{by:.4g} B"}
+    # Whole-matvec algorithmic bytes 24 K^3 + 48 N per probe-vector.
+    bmv = 24.0 * K[0] * K[1] * K[2] + 48.0 * s.n
+    path_gbs = bmv * value / 1e9
+    plan.close()
+
+    # Plain form: one probe vector at a time in float64, same kernels, same GPU.
+    Rp = args.plain_probes
+    prm_p = P.Params(real_cutoff=wl.real_cutoff_angstrom * A, grid=K, n_probes=Rp, n_steps=m,
+                     block=1, precision=P.PREC_FP64, seed=wl.probe_seed)
+    plain = P.Plan([ds], prm_p)
+    plain.execute()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain.execute()
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    plain.check()
+    plain_rate = Rp * m / tp
+    plain.close()
+    log(f"plain fp64 B=1: {plain_rate:.1f} matvecs/s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import method as om
+        threads = torch.get_num_threads()
+        op = om.Operator(s, om.MethodParams(tau=info.tau, r_pair=info.r_pair, grid=K,
+                                            order=info.spline_order))
+        y = torch.randn(s.n, 3, 1, dtype=torch.float64, generator=torch.Generator().manual_seed(0))
+        nmv = 12
+        t0 = time.perf_counter()
+        for _ in range(nmv):
+            op(y)
+        tc = time.perf_counter() - t0
+        cpu = {"value": round(nmv / tc, 4), "unit": "matvecs/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"{nmv} single-vector float64 SPME matvecs (same N, K, p, tau, r_pair) "
+                         f"with the CPU oracle, {tc:.1f} s"}
+        log(f"cpu oracle: {nmv / tc:.3f} matvecs/s on {threads} threads")
+
+    out = {
+        "metric": "probe-vector SPME matvecs/s at N=24k (batched, mixed precision)",
+        "value": round(value, 1),
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "water box N=24000, L=62.09 A, K=96^3, p=6, r_c=9 A, "
+                               "128 probes x 50 Lanczos steps as one RHS block",
+                   "n_atoms": s.n, "grid": list(K), "probes": R, "lanczos_steps": m,
+                   "block": B, "pairs": n_pairs},
+        "energy_ms": round(ms_per_step, 3),
+        "energy_ha": energy,
+        "plain_matvecs_per_s": round(plain_rate, 2),
+        "speedup_vs_plain": round(value / plain_rate, 2),
+        "path_algorithmic_GBps": round(path_gbs, 1),
+        "path_roofline_frac": round(path_gbs / HBM_PEAK_GBS, 4),
+        "stage_ms_per_step": {k: round(v, 3) for k, v in stage_ms.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

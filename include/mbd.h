@@ -108,6 +108,7 @@ typedef struct {
   int32_t cells[3];     /* cell-list cells per axis                                    */
   int32_t block;        /* right-hand sides per block                                  */
   size_t workspace_bytes;
+  int64_t n_pairs;      /* directed (i, j, image) pairs within r_pair at the current positions */
 } mbd_info;
 
 /* Probe definition (eq. dds): entry (l, i, a) of system s is +-1/sqrt(3N), the sign
@@ -124,9 +125,16 @@ typedef struct {
 mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_sys,
                            const mbd_params* prm, void* stream);
 
+/* Derived parameters of one system (synchronizes the plan's stream: n_pairs is counted
+ * on the device at the current positions). */
 mbd_status mbd_plan_info(mbd_plan plan, int32_t sys, mbd_info* info);
 
-/* Re-run the position-dependent setup with new positions (device [N][3]) for one system. */
+/* Re-run the position-dependent device setup (wrap, cell sort, spline tables, tile
+ * lists; Algorithm 1 neighbour-list step) with new positions for one system.
+ * pos: device [N][3] bohr, caller-owned; it is read during this call's stream work
+ * and not retained. The alpha/omega/r_vdw arrays given at plan creation are read
+ * again, so they must still be alive. The cell list keeps the cell counts chosen at
+ * creation, which stay valid for any positions in the same cell. */
 mbd_status mbd_set_positions(mbd_plan plan, int32_t sys, const double* pos);
 
 /* Run Algorithm 1 for every system: R probes in blocks of `block` RHS, m Lanczos steps
@@ -159,6 +167,27 @@ mbd_status mbd_plan_destroy(mbd_plan plan);
 
 /* 1 if an FFT of length k is compiled in (even 2^a 3^b 5^c in [8, 128]), else 0. */
 int32_t mbd_grid_supported(int32_t k);
+
+/* Stage timing (diagnostic). Stages, in pipeline order: */
+enum {
+  MBD_STAGE_PAIR = 0,      /* direct-space pair kernel                        */
+  MBD_STAGE_SPREAD = 1,    /* B-spline spreading of the dipoles               */
+  MBD_STAGE_FFT_X = 2,     /* forward real-to-complex transform along x       */
+  MBD_STAGE_FFT_Y = 3,     /* forward transform along y                       */
+  MBD_STAGE_FFT_Z = 4,     /* transform along z, convolution, inverse along z */
+  MBD_STAGE_IFFT_Y = 5,    /* inverse transform along y                       */
+  MBD_STAGE_IFFT_X = 6,    /* inverse complex-to-real transform along x       */
+  MBD_STAGE_GATHER = 7,    /* derivative gather + epilogue (l = Omega w + g E*) */
+  MBD_STAGE_LANCZOS = 8,   /* recurrence update, reductions, quadrature        */
+  MBD_STAGE_SETUP = 9,     /* position-dependent setup                         */
+  MBD_N_STAGES = 10
+};
+/* enable != 0: from now on every stage launch enqueued by this plan is bracketed by
+ * HIP events on the plan's stream (adds a few microseconds per launch). */
+mbd_status mbd_set_timing(mbd_plan plan, int32_t enable);
+/* Synchronize, then return per-stage total milliseconds ms[MBD_N_STAGES] and launch
+ * counts launches[MBD_N_STAGES] recorded since the last call (host arrays), and reset. */
+mbd_status mbd_get_stage_times(mbd_plan plan, double* ms, int64_t* launches);
 
 const char* mbd_status_string(mbd_status s);
 const char* mbd_last_error(void);

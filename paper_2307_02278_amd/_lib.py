@@ -14,6 +14,8 @@ MBD_E_NODEVICE, MBD_E_HIP, MBD_E_OOM, MBD_E_STATE = -6, -7, -8, -9
 PREC_FP64, PREC_MIXED = 0, 1
 REORTH_NONE, REORTH_LOCAL, REORTH_FULL = 0, 1, 2
 C_DIAG, C_DIR, C_REC, C_SELF, C_ALL = 1, 2, 4, 8, 15
+STAGES = ["pair", "spread", "fft_x", "fft_y", "fft_z_conv", "ifft_y", "ifft_x", "gather",
+          "lanczos", "setup"]
 
 
 class MbdSystem(C.Structure):
@@ -56,6 +58,7 @@ class MbdInfo(C.Structure):
         ("cells", C.c_int32 * 3),
         ("block", C.c_int32),
         ("workspace_bytes", C.c_size_t),
+        ("n_pairs", C.c_int64),
     ]
 
 
@@ -75,6 +78,9 @@ SIGNATURES = [
     ("mbd_get_quadrature", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
     ("mbd_plan_destroy", C.c_int32, [C.c_void_p]),
     ("mbd_grid_supported", C.c_int32, [C.c_int32]),
+    ("mbd_set_timing", C.c_int32, [C.c_void_p, C.c_int32]),
+    ("mbd_get_stage_times", C.c_int32,
+     [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     ("mbd_status_string", C.c_char_p, [C.c_int32]),
     ("mbd_last_error", C.c_char_p, []),
 ]

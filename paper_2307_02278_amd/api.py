@@ -130,6 +130,22 @@ class Plan:
         L.check(self.lib.mbd_get_quadrature(self.handle, sys, q))
         return torch.tensor(list(q), dtype=torch.float64)
 
+    def set_positions(self, pos: torch.Tensor, sys: int = 0):
+        pos = pos.to(dtype=torch.float64, device="cuda").contiguous()
+        self._pos_keep = pos
+        L.check(self.lib.mbd_set_positions(self.handle, sys, C.c_void_p(pos.data_ptr())))
+
+    def set_timing(self, on: bool = True):
+        L.check(self.lib.mbd_set_timing(self.handle, 1 if on else 0))
+
+    def stage_times(self):
+        """{stage: (total_ms, launches)} since the last call."""
+        n = len(L.STAGES)
+        ms = (C.c_double * n)()
+        cnt = (C.c_int64 * n)()
+        L.check(self.lib.mbd_get_stage_times(self.handle, ms, cnt))
+        return {L.STAGES[i]: (ms[i], cnt[i]) for i in range(n)}
+
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             self.lib.mbd_plan_destroy(self.handle)

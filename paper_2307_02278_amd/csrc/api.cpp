@@ -162,18 +162,42 @@ void allocate_system(Plan& plan, System& S, int R_probes, int m) {
   check(hipMemcpy(b.tw, tw.data(), tw.size() * sizeof(R), hipMemcpyHostToDevice), "copy tw");
 }
 
+// Bracket the launches made by f with events when stage timing is on.
+template <typename F>
+void staged(Plan& plan, int stage, F&& f) {
+  if (!plan.timer.on) {
+    f();
+    return;
+  }
+  hipEvent_t a = plan.timer.next(), b = plan.timer.next();
+  check(hipEventRecord(a, plan.stream), "event record");
+  f();
+  check(hipEventRecord(b, plan.stream), "event record");
+  plan.timer.recs.push_back({stage, a, b});
+}
+
 template <typename R>
-void run_setup(Plan& plan, System& S, const mbd_system& src, const double* pos) {
-  launch_setup<R>(S.geo, S.buf, pos, src.alpha, src.omega, src.r_vdw, plan.stream);
+void run_setup(Plan& plan, System& S, const double* pos) {
+  staged(plan, MBD_STAGE_SETUP, [&] {
+    launch_setup<R>(S.geo, S.buf, pos, S.src.alpha, S.src.omega, S.src.r_vdw, plan.stream);
+  });
 }
 
 // One application of C to the block stored at w (internal layout), into Lt.
 template <typename R>
 void matvec_block(Plan& plan, System& S, const double* w, uint32_t comps) {
   const hipStream_t st = plan.stream;
-  if (comps & MBD_C_DIR) launch_pair<R>(S.geo, S.buf, plan.B, st);
-  if (comps & MBD_C_REC) launch_spme<R>(S.geo, S.buf, plan.B, plan.BG, st);
-  launch_epilogue<R>(S.geo, S.buf, w, plan.B, plan.BG, comps, st);
+  if (comps & MBD_C_DIR)
+    staged(plan, MBD_STAGE_PAIR, [&] { launch_pair<R>(S.geo, S.buf, plan.B, st); });
+  if (comps & MBD_C_REC) {
+    staged(plan, MBD_STAGE_SPREAD,
+           [&] { launch_spread<R>(S.geo, S.buf, plan.B, plan.BG, st); });
+    for (int pass = 0; pass < 5; ++pass)
+      staged(plan, MBD_STAGE_FFT_X + pass,
+             [&] { launch_fft_pass<R>(S.geo, S.buf, plan.B, plan.BG, pass, st); });
+  }
+  staged(plan, MBD_STAGE_GATHER,
+         [&] { launch_epilogue<R>(S.geo, S.buf, w, plan.B, plan.BG, comps, st); });
 }
 
 template <typename R>
@@ -184,26 +208,32 @@ void run_energy(Plan& plan, System& S, int sys_index, double* energy) {
   const size_t vs = 3 * (size_t)S.geo.n * B;
   for (int l0 = 0; l0 < R_probes; l0 += B) {
     const int nb = std::min(B, R_probes - l0);
-    launch_init_scalars(S.buf, nb, m, l0, st);
-    launch_probes(S.geo, S.buf, B, nb, l0, plan.prm.seed, sys_index, fl, st);
+    staged(plan, MBD_STAGE_LANCZOS, [&] {
+      launch_init_scalars(S.buf, nb, m, l0, st);
+      launch_probes(S.geo, S.buf, B, nb, l0, plan.prm.seed, sys_index, fl, st);
+    });
     for (int k = 0; k < m; ++k) {
       matvec_block<R>(plan, S, S.buf.W + (size_t)k * vs, MBD_C_ALL);
-      launch_finish_a(S.buf, B, nb, k, m, l0, plan.status, st);
-      if (k + 1 < m) {
-        const int ro = plan.prm.reorth;
-        launch_update(S.geo, S.buf, B, nb, k, m, l0, fl, ro == MBD_REORTH_NONE, st);
-        if (ro == MBD_REORTH_LOCAL) {
-          launch_reorth(S.geo, S.buf, B, nb, k, m, l0, std::max(0, k - 1), fl, st);
-        } else if (ro == MBD_REORTH_FULL) {
-          launch_reorth(S.geo, S.buf, B, nb, k, m, l0, 0, fl, st);
-          launch_reorth(S.geo, S.buf, B, nb, k, m, l0, 0, fl, st);
+      staged(plan, MBD_STAGE_LANCZOS, [&] {
+        launch_finish_a(S.buf, B, nb, k, m, l0, plan.status, st);
+        if (k + 1 < m) {
+          const int ro = plan.prm.reorth;
+          launch_update(S.geo, S.buf, B, nb, k, m, l0, fl, ro == MBD_REORTH_NONE, st);
+          if (ro == MBD_REORTH_LOCAL) {
+            launch_reorth(S.geo, S.buf, B, nb, k, m, l0, std::max(0, k - 1), fl, st);
+          } else if (ro == MBD_REORTH_FULL) {
+            launch_reorth(S.geo, S.buf, B, nb, k, m, l0, 0, fl, st);
+            launch_reorth(S.geo, S.buf, B, nb, k, m, l0, 0, fl, st);
+          }
+          launch_finish_norm(S.buf, B, nb, k, m, l0, plan.status, st);
         }
-        launch_finish_norm(S.buf, B, nb, k, m, l0, plan.status, st);
-      }
+      });
     }
-    launch_tridiag(S.buf, nb, m, l0, plan.status, st);
+    staged(plan, MBD_STAGE_LANCZOS,
+           [&] { launch_tridiag(S.buf, nb, m, l0, plan.status, st); });
   }
-  launch_energy(S.geo, S.buf, R_probes, energy, plan.status, st);
+  staged(plan, MBD_STAGE_LANCZOS,
+         [&] { launch_energy(S.geo, S.buf, R_probes, energy, plan.status, st); });
 }
 
 mbd_status fail(mbd_status code, const std::string& msg) {
@@ -214,6 +244,15 @@ mbd_status fail(mbd_status code, const std::string& msg) {
 }  // namespace
 
 void set_error(const std::string& msg) { g_last_error = msg; }
+
+hipEvent_t StageTimer::next() {
+  if (used == pool.size()) {
+    hipEvent_t e;
+    check(hipEventCreate(&e), "event create");
+    pool.push_back(e);
+  }
+  return pool[used++];
+}
 
 }  // namespace mbd
 
@@ -358,6 +397,7 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
         }
         rmax = std::max(rmax, rv[i]);
       }
+      S.src = sy;
       Geometry& g = S.geo;
       double rp = prm.real_cutoff;
       if (prm.damp_tol >= 0.0) {
@@ -374,10 +414,10 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
       }
       if (plan.prec == MBD_PREC_FP64) {
         allocate_system<double>(plan, S, prm.n_probes, prm.n_steps);
-        run_setup<double>(plan, S, sy, sy.pos);
+        run_setup<double>(plan, S, sy.pos);
       } else {
         allocate_system<float>(plan, S, prm.n_probes, prm.n_steps);
-        run_setup<float>(plan, S, sy, sy.pos);
+        run_setup<float>(plan, S, sy.pos);
       }
       check(hipGetLastError(), "setup launch");
     }
@@ -408,12 +448,51 @@ mbd_status mbd_plan_info(mbd_plan plan, int32_t sys, mbd_info* info) {
   info->spline_order = g.p;
   info->block = P.B;
   info->workspace_bytes = P.sys[sys].bytes;
+  info->n_pairs = P.prec == MBD_PREC_FP64
+                      ? mbd::count_pairs<double>(g, P.sys[sys].buf, P.stream)
+                      : mbd::count_pairs<float>(g, P.sys[sys].buf, P.stream);
+  if (info->n_pairs < 0) return fail(MBD_E_HIP, "pair count failed");
   return MBD_OK;
 }
 
 mbd_status mbd_set_positions(mbd_plan plan, int32_t sys, const double* pos) {
-  (void)plan; (void)sys; (void)pos;
-  return fail(MBD_E_STATE, "set_positions needs the parameter arrays; not available yet");
+  using namespace mbd;
+  if (!plan || !pos) return fail(MBD_E_ARG, "NULL argument");
+  Plan& P = plan->plan;
+  if (sys < 0 || sys >= (int)P.sys.size()) return fail(MBD_E_ARG, "system index out of range");
+  try {
+    if (P.prec == MBD_PREC_FP64) run_setup<double>(P, P.sys[sys], pos);
+    else run_setup<float>(P, P.sys[sys], pos);
+    check(hipGetLastError(), "setup launch");
+  } catch (const HipError& e) {
+    return fail(MBD_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
+  return MBD_OK;
+}
+
+mbd_status mbd_set_timing(mbd_plan plan, int32_t enable) {
+  if (!plan) return fail(MBD_E_ARG, "NULL plan");
+  plan->plan.timer.on = enable != 0;
+  return MBD_OK;
+}
+
+mbd_status mbd_get_stage_times(mbd_plan plan, double* ms, int64_t* launches) {
+  if (!plan || !ms || !launches) return fail(MBD_E_ARG, "NULL argument");
+  mbd::Plan& P = plan->plan;
+  if (hipStreamSynchronize(P.stream) != hipSuccess) return fail(MBD_E_HIP, "synchronize failed");
+  for (int i = 0; i < MBD_N_STAGES; ++i) {
+    ms[i] = 0.0;
+    launches[i] = 0;
+  }
+  for (const auto& r : P.timer.recs) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return fail(MBD_E_HIP, "event time");
+    ms[r.stage] += t;
+    launches[r.stage] += 1;
+  }
+  P.timer.recs.clear();
+  P.timer.used = 0;
+  return MBD_OK;
 }
 
 mbd_status mbd_execute(mbd_plan plan, double* energy, double* forces) {
@@ -501,6 +580,7 @@ mbd_status mbd_get_quadrature(mbd_plan plan, int32_t sys, double* q) {
 mbd_status mbd_plan_destroy(mbd_plan plan) {
   if (!plan) return MBD_OK;
   hipStreamSynchronize(plan->plan.stream);
+  for (hipEvent_t e : plan->plan.timer.pool) hipEventDestroy(e);
   for (void* p : plan->plan.allocations) hipFree(p);
   delete plan;
   return MBD_OK;

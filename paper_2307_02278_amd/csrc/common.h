@@ -73,8 +73,19 @@ struct SysBuffers {
 struct System {
   Geometry geo;
   SysBuffers buf;
+  mbd_system src;              // caller's arrays (alpha, omega, r_vdw stay caller-owned)
   double host_cell[9];
   size_t bytes = 0;
+};
+
+// Optional per-stage event timing on the plan's stream.
+struct StageTimer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Rec { int stage; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  hipEvent_t next();
 };
 
 struct Plan {
@@ -88,6 +99,7 @@ struct Plan {
   uint32_t* status = nullptr;  // device status word
   bool executed = false;
   std::vector<void*> allocations;
+  StageTimer timer;
 };
 
 // ---------------------------------------------------------------------------
@@ -101,7 +113,14 @@ template <typename R>
 void launch_pair(const Geometry& g, const SysBuffers& b, int B, hipStream_t st);
 
 template <typename R>
-void launch_spme(const Geometry& g, const SysBuffers& b, int B, int BG, hipStream_t st);
+long long count_pairs(const Geometry& g, const SysBuffers& b, hipStream_t st);
+
+template <typename R>
+void launch_spread(const Geometry& g, const SysBuffers& b, int B, int BG, hipStream_t st);
+
+template <typename R>
+void launch_fft_pass(const Geometry& g, const SysBuffers& b, int B, int BG, int pass,
+                     hipStream_t st);
 
 void fill_int(int* p, int v, int n, hipStream_t st);
 

@@ -294,9 +294,11 @@ bool fft_supported(int k) {
   }
 }
 
-// Forward transform of every chunk, convolution with G, inverse transform.
+// One pass (0 forward x, 1 forward y, 2 z with convolution, 3 inverse y, 4 inverse x)
+// over every grid chunk.
 template <typename R>
-void launch_fft_conv(const Geometry& geo, const SysBuffers& b, int B, int BG, hipStream_t st) {
+void launch_fft_pass(const Geometry& geo, const SysBuffers& b, int B, int BG, int pass,
+                     hipStream_t st) {
   GridDims gd;
   gd.K1 = geo.K[0];
   gd.K2 = geo.K[1];
@@ -312,18 +314,19 @@ void launch_fft_conv(const Geometry& geo, const SysBuffers& b, int B, int BG, hi
   const R* c0 = tw;
   const R* c1 = tw + geo.K[0];
   const R* c2 = tw + geo.K[0] + geo.K[1];
-  const R* s0 = c0 + Ksum;
-  const R* s1 = c1 + Ksum;
-  const R* s2 = c2 + Ksum;
   const R* G = (const R*)b.G;
-  launch_pass<R, kXFwd>(geo.K[0], grid, gd, nchunks, c0, s0, G, st);
-  launch_pass<R, kYFwd>(geo.K[1], grid, gd, nchunks, c1, s1, G, st);
-  launch_pass<R, kZConv>(geo.K[2], grid, gd, nchunks, c2, s2, G, st);
-  launch_pass<R, kYInv>(geo.K[1], grid, gd, nchunks, c1, s1, G, st);
-  launch_pass<R, kXInv>(geo.K[0], grid, gd, nchunks, c0, s0, G, st);
+  switch (pass) {
+    case 0: launch_pass<R, kXFwd>(geo.K[0], grid, gd, nchunks, c0, c0 + Ksum, G, st); break;
+    case 1: launch_pass<R, kYFwd>(geo.K[1], grid, gd, nchunks, c1, c1 + Ksum, G, st); break;
+    case 2: launch_pass<R, kZConv>(geo.K[2], grid, gd, nchunks, c2, c2 + Ksum, G, st); break;
+    case 3: launch_pass<R, kYInv>(geo.K[1], grid, gd, nchunks, c1, c1 + Ksum, G, st); break;
+    default: launch_pass<R, kXInv>(geo.K[0], grid, gd, nchunks, c0, c0 + Ksum, G, st); break;
+  }
 }
 
-template void launch_fft_conv<float>(const Geometry&, const SysBuffers&, int, int, hipStream_t);
-template void launch_fft_conv<double>(const Geometry&, const SysBuffers&, int, int, hipStream_t);
+template void launch_fft_pass<float>(const Geometry&, const SysBuffers&, int, int, int,
+                                     hipStream_t);
+template void launch_fft_pass<double>(const Geometry&, const SysBuffers&, int, int, int,
+                                      hipStream_t);
 
 }  // namespace mbd

@@ -176,7 +176,55 @@ k_pair_tiled(const Geometry geo, const int* __restrict__ cell_start, const R* __
   }
 }
 
+template <typename R>
+__global__ void k_count_pairs(const Geometry geo, const int* __restrict__ cell_start,
+                              const int* __restrict__ scell, const R* __restrict__ loc,
+                              unsigned long long* __restrict__ count) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= geo.n) return;
+  const int c = scell[s];
+  const int cx = c % geo.nc[0], cy = (c / geo.nc[0]) % geo.nc[1], cz = c / (geo.nc[0] * geo.nc[1]);
+  const R xi = loc[4 * s], yi = loc[4 * s + 1], zi = loc[4 * s + 2];
+  const R rp2 = (R)(geo.r_pair * geo.r_pair);
+  unsigned long long cnt = 0;
+  for (int oz = -geo.nr[2]; oz <= geo.nr[2]; ++oz) {
+    int wz = ((cz + oz) % geo.nc[2] + geo.nc[2]) % geo.nc[2];
+    for (int oy = -geo.nr[1]; oy <= geo.nr[1]; ++oy) {
+      int wy = ((cy + oy) % geo.nc[1] + geo.nc[1]) % geo.nc[1];
+      for (int ox = -geo.nr[0]; ox <= geo.nr[0]; ++ox) {
+        int wx = ((cx + ox) % geo.nc[0] + geo.nc[0]) % geo.nc[0];
+        const bool zero = (ox == 0 && oy == 0 && oz == 0);
+        const int cc = (wz * geo.nc[1] + wy) * geo.nc[0] + wx;
+        for (int j = cell_start[cc]; j < cell_start[cc + 1]; ++j) {
+          if (zero && j == s) continue;
+          const R rx = loc[4 * j] - xi + (R)(ox * geo.hc[0]);
+          const R ry = loc[4 * j + 1] - yi + (R)(oy * geo.hc[1]);
+          const R rz = loc[4 * j + 2] - zi + (R)(oz * geo.hc[2]);
+          cnt += (rx * rx + ry * ry + rz * rz < rp2) ? 1 : 0;
+        }
+      }
+    }
+  }
+  atomicAdd(count, cnt);
+}
+
 }  // namespace
+
+template <typename R>
+long long count_pairs(const Geometry& g, const SysBuffers& b, hipStream_t st) {
+  unsigned long long* d = nullptr;
+  unsigned long long h = 0;
+  if (hipMalloc(&d, sizeof(h)) != hipSuccess) return -1;
+  hipMemsetAsync(d, 0, sizeof(h), st);
+  k_count_pairs<R><<<(g.n + 127) / 128, 128, 0, st>>>(g, b.cell_start, b.scell, (const R*)b.loc, d);
+  hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, st);
+  hipStreamSynchronize(st);
+  hipFree(d);
+  return (long long)h;
+}
+
+template long long count_pairs<float>(const Geometry&, const SysBuffers&, hipStream_t);
+template long long count_pairs<double>(const Geometry&, const SysBuffers&, hipStream_t);
 
 template <typename R>
 void launch_pair(const Geometry& g, const SysBuffers& b, int B, hipStream_t st) {

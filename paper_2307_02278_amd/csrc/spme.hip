@@ -161,10 +161,7 @@ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 }  // namespace
 
 template <typename R>
-void launch_fft_conv(const Geometry& geo, const SysBuffers& b, int B, int BG, hipStream_t st);
-
-template <typename R>
-void launch_spme(const Geometry& geo, const SysBuffers& b, int B, int BG, hipStream_t st) {
+void launch_spread(const Geometry& geo, const SysBuffers& b, int B, int BG, hipStream_t st) {
   const size_t chunk = (size_t)geo.K[2] * geo.K[1] * (geo.K[0] + 2) * BG;
   const int ntiles = geo.tiles[0] * geo.tiles[1] * geo.tiles[2];
   dim3 grd(ntiles, B / BG);
@@ -190,7 +187,6 @@ void launch_spme(const Geometry& geo, const SysBuffers& b, int B, int BG, hipStr
   }
 #undef MBD_SPREAD_P
 #undef MBD_SPREAD
-  launch_fft_conv<R>(geo, b, B, BG, st);
 }
 
 template <typename R>
@@ -221,8 +217,8 @@ void launch_epilogue(const Geometry& geo, const SysBuffers& b, const double* w, 
 #undef MBD_GATHER
 }
 
-template void launch_spme<float>(const Geometry&, const SysBuffers&, int, int, hipStream_t);
-template void launch_spme<double>(const Geometry&, const SysBuffers&, int, int, hipStream_t);
+template void launch_spread<float>(const Geometry&, const SysBuffers&, int, int, hipStream_t);
+template void launch_spread<double>(const Geometry&, const SysBuffers&, int, int, hipStream_t);
 template void launch_epilogue<float>(const Geometry&, const SysBuffers&, const double*, int, int,
                                      uint32_t, hipStream_t);
 template void launch_epilogue<double>(const Geometry&, const SysBuffers&, const double*, int, int,
