@@ -84,7 +84,7 @@ typedef struct {
   double ewald_tau;     /* Ewald splitting tau in 1/bohr; <= 0: derived from real_cutoff
                            by erfc(tau r_c) / r_c = 1e-8 with r_c in Angstrom           */
   double real_cutoff;   /* erfc cutoff r_c in bohr (> 0)                               */
-  double damp_tol;      /* pair kernel also runs to where 1 - f = damp_tol; 0 => 1e-7;
+  double damp_tol;      /* pair kernel also runs to where 1 - f = damp_tol; 0 => 1e-4;
                            < 0 => only real_cutoff is used                              */
   int32_t grid[3];      /* SPME grid K1..K3; 0 => smallest even 2^a 3^b >= 1.4 / A     */
   int32_t spline_order; /* B-spline order p (support of p points): even, 4..8; 0 => 6   */

@@ -17,7 +17,7 @@ class Params:
     damp_d: float = 6.0
     ewald_tau: float = 0.0          # 1/bohr; 0 => from real_cutoff
     real_cutoff: float = 9.0 / 0.529177210903
-    damp_tol: float = 0.0           # 0 => 1e-7
+    damp_tol: float = 0.0           # 0 => 1e-4
     grid: Sequence[int] = (0, 0, 0)
     spline_order: int = 6
     n_probes: int = 8

@@ -140,7 +140,10 @@ void allocate_system(Plan& plan, System& S, int R_probes, int m) {
   b.dth = dalloc<R>(plan, 3 * (size_t)n * g.p, by);
   b.tile_count = dalloc<int>(plan, ntiles + 1, by);
   b.tile_start = dalloc<int>(plan, ntiles + 1, by);
-  b.tile_atoms = dalloc<int>(plan, 27 * (size_t)n, by);
+  // at most ceil((p - 1) / tile) + 2 tiles per axis touched by one stencil
+  size_t per_atom = 1;
+  for (int a = 0; a < 3; ++a) per_atom *= (size_t)((g.p - 1 + g.tile[a] - 1) / g.tile[a] + 2);
+  b.tile_atoms = dalloc<int>(plan, per_atom * (size_t)n, by);
   b.G = dalloc<R>(plan, (size_t)g.K[2] * g.K[1] * (g.K[0] / 2 + 1), by);
   b.tw = dalloc<R>(plan, 2 * (size_t)(g.K[0] + g.K[1] + g.K[2]), by);
   const size_t vec = 3 * (size_t)n * B;
@@ -322,6 +325,7 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
   for (int a = 0; a < 3; ++a)
     if (prm.grid[a] < 0) return fail(MBD_E_ARG, "grid sizes must be >= 0");
 
+  const int BG_plan = std::min(prm.block, prm.precision == MBD_PREC_FP64 ? 16 : 64);
   std::vector<Geometry> geos(n_sys);
   for (int s = 0; s < n_sys; ++s) {
     const mbd_system& sy = systems[s];
@@ -348,8 +352,10 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
                                      " unsupported (even 2^a 3^b 5^c in [8, 128])");
       if (K < 2 * g.p) return fail(MBD_E_GRID, "grid must be >= 2 p");
       g.K[a] = K;
-      g.tiles[a] = (K + kSpreadTile - 1) / kSpreadTile;
     }
+    // Spread tiles: 4x4x4 grid points, one wavefront each.
+    g.tile[0] = g.tile[1] = g.tile[2] = kSpreadTile;
+    for (int a = 0; a < 3; ++a) g.tiles[a] = (g.K[a] + g.tile[a] - 1) / g.tile[a];
     g.tau = prm.ewald_tau > 0.0
                 ? prm.ewald_tau
                 : tau_from_cutoff_angstrom(prm.real_cutoff * kBohrAngstrom) * kBohrAngstrom;
@@ -367,7 +373,7 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
   plan.prm = prm;
   plan.prec = prm.precision;
   plan.B = prm.block;
-  plan.BG = std::min(plan.B, plan.prec == MBD_PREC_FP64 ? 16 : 32);
+  plan.BG = BG_plan;
   plan.stream = static_cast<hipStream_t>(stream);
   hipGetDevice(&plan.device);
   try {
@@ -401,7 +407,7 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
       Geometry& g = S.geo;
       double rp = prm.real_cutoff;
       if (prm.damp_tol >= 0.0) {
-        const double tol = prm.damp_tol > 0.0 ? prm.damp_tol : 1e-7;
+        const double tol = prm.damp_tol > 0.0 ? prm.damp_tol : 1e-4;
         const double smax = prm.damp_beta * 2.0 * rmax;
         rp = std::max(rp, smax * (1.0 + std::log(1.0 / tol - 1.0) / prm.damp_d));
       }

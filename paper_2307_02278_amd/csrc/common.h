@@ -13,8 +13,8 @@
 namespace mbd {
 
 constexpr int kMaxOrder = 8;
-constexpr int kSpreadTile = 8;     // grid points per tile edge in the spread kernel
-constexpr int kRedBlocks = 256;    // blocks (and partial sums) of the Lanczos reductions
+constexpr int kRedBlocks = 1024;   // blocks (and partial sums) of the row reductions
+constexpr int kSpreadTile = 4;     // grid points per spread-tile edge (one wavefront per tile)
 constexpr int kMaxSteps = 512;
 
 // Device-side error bits (status word).
@@ -31,6 +31,7 @@ struct Geometry {
   int nc[3];             // cells per axis
   double hc[3];          // cell edge per axis
   int nr[3];             // neighbour-cell range per axis
+  int tile[3];           // spread tile edge per axis (grid points)
   int tiles[3];          // spread tiles per axis
   double beta, damp_d;
 };
@@ -52,7 +53,7 @@ struct SysBuffers {
   void* dth = nullptr;         // Real [n][3][p] (K_a / L_a) M_p'(w + t)
   int* tile_count = nullptr;   // [ntiles + 1]
   int* tile_start = nullptr;   // [ntiles + 1]
-  int* tile_atoms = nullptr;   // [27 n]
+  int* tile_atoms = nullptr;   // [n * max tiles per stencil]
   void* G = nullptr;           // Real [K3][K2][K1/2 + 1]
   void* tw = nullptr;          // Real [2][K1 + K2 + K3] twiddles exp(-2 pi i j / K_a)
   // Lanczos state for one block of right-hand sides

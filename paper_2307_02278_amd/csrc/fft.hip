@@ -251,6 +251,248 @@ k_fft(R* __restrict__ grid, GridDims gd, const R* __restrict__ twc,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident variant (float32): a lane pair owns one column (a line of K
+// points for one right-hand side) and runs the Stockham stages on registers, with
+// twiddles folded to compile-time constants. Consecutive lane pairs are
+// consecutive right-hand sides, so every load and store of a wavefront touches
+// two contiguous rows; there is no LDS traffic and no barrier.
+// ---------------------------------------------------------------------------
+constexpr double cx_sin_core(double x) {
+  // x in [-pi, pi]; Taylor series to well below double rounding
+  double term = x, sum = x;
+  for (int n = 1; n < 40; ++n) {
+    term *= -x * x / ((2.0 * n) * (2.0 * n + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double cx_sin(double x) {
+  while (x > kPi) x -= 2 * kPi;
+  while (x < -kPi) x += 2 * kPi;
+  return cx_sin_core(x);
+}
+constexpr double cx_cos(double x) { return cx_sin(x + kPi / 2); }
+
+template <int K>
+struct TwTable {
+  float c[K];
+  float s[K];
+  constexpr TwTable() : c(), s() {
+    for (int j = 0; j < K; ++j) {
+      c[j] = (float)cx_cos(2.0 * kPi * j / K);
+      s[j] = (float)cx_sin(2.0 * kPi * j / K);
+    }
+  }
+};
+
+template <int K, int S, bool FWD>
+__device__ __forceinline__ void reg_stages(float (&xr)[K], float (&xi)[K]) {
+  constexpr Radices F = factorize(K);
+  if constexpr (S < F.n) {
+    constexpr int r = F.r[S];
+    constexpr int NB = K / r;
+    constexpr int Ns = prefix_product(K, S);
+    constexpr int TWS = K / (Ns * r);
+    constexpr TwTable<K> T{};
+    float yr[K], yi[K];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int k = j % Ns;
+      float vr[r], vi[r];
+#pragma unroll
+      for (int t = 0; t < r; ++t) {
+        float ar = xr[j + t * NB], ai = xi[j + t * NB];
+        if (t > 0 && k > 0) {
+          const int idx = k * t * TWS;
+          const float wc = T.c[idx];
+          const float ws = FWD ? -T.s[idx] : T.s[idx];
+          const float br = ar * wc - ai * ws;
+          ai = ar * ws + ai * wc;
+          ar = br;
+        }
+        vr[t] = ar;
+        vi[t] = ai;
+      }
+      small_dft<float, r, FWD>(vr, vi);
+      const int base = (j / Ns) * Ns * r + k;
+#pragma unroll
+      for (int t = 0; t < r; ++t) {
+        yr[base + t * Ns] = vr[t];
+        yi[base + t * Ns] = vi[t];
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < K; ++n) {
+      xr[n] = yr[n];
+      xi[n] = yi[n];
+    }
+    reg_stages<K, S + 1, FWD>(xr, xi);
+  }
+}
+
+// One column is split over a lane pair (h = lane & 1): lane h holds the decimated
+// samples x[2m + h], m < H = K/2, runs an H-point FFT in registers, and the pair
+// finishes with one radix-2 step exchanged through a lane shuffle:
+//   decimation in time:  X[k] = F0[k] + W^k F1[k],  X[k + H] = F0[k] - W^k F1[k]
+//   (lane 0 ends with X[0..H), lane 1 with X[H..K));
+//   decimation in frequency (used after the convolution, from natural halves):
+//   y0[k] = x[k] + x[k + H], y1[k] = (x[k] - x[k + H]) W^k, then H-point FFTs give
+//   X[2k] (lane 0) and X[2k + 1] (lane 1).
+template <int K, bool FWD>
+__device__ __forceinline__ void pair_dit(float (&xr)[K / 2], float (&xi)[K / 2], int h) {
+  constexpr int H = K / 2;
+  constexpr TwTable<K> T{};
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    const float pr = __shfl_xor(xr[k], 1), pi = __shfl_xor(xi[k], 1);
+    const float er = h ? pr : xr[k], ei = h ? pi : xi[k];
+    const float orr = h ? xr[k] : pr, oi = h ? xi[k] : pi;
+    const float wc = T.c[k], ws = FWD ? -T.s[k] : T.s[k];
+    const float tr = orr * wc - oi * ws, ti = orr * ws + oi * wc;
+    xr[k] = h ? er - tr : er + tr;
+    xi[k] = h ? ei - ti : ei + ti;
+  }
+}
+
+template <int K, bool FWD>
+__device__ __forceinline__ void pair_dif(float (&xr)[K / 2], float (&xi)[K / 2], int h) {
+  constexpr int H = K / 2;
+  constexpr TwTable<K> T{};
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    const float pr = __shfl_xor(xr[k], 1), pi = __shfl_xor(xi[k], 1);
+    // lane 0 holds x[k], lane 1 holds x[k + H]
+    const float ar = h ? pr : xr[k], ai = h ? pi : xi[k];
+    const float br = h ? xr[k] : pr, bi = h ? xi[k] : pi;
+    if (h == 0) {
+      xr[k] = ar + br;
+      xi[k] = ai + bi;
+    } else {
+      const float dr = ar - br, di = ai - bi;
+      const float wc = T.c[k], ws = FWD ? -T.s[k] : T.s[k];
+      xr[k] = dr * wc - di * ws;
+      xi[k] = dr * ws + di * wc;
+    }
+  }
+}
+
+template <int K, int MODE>
+__global__ void __launch_bounds__(64)
+k_fft_reg(float* __restrict__ grid, GridDims gd, const float* __restrict__ G) {
+  constexpr int H = K / 2;
+  float* g = grid + (size_t)blockIdx.y * gd.chunk_elems;
+  const int h = threadIdx.x & 1;
+  const long col = (long)blockIdx.x * 32 + (threadIdx.x >> 1);
+  const int BG = gd.BG;
+  const int b = (int)(col % BG);
+  const long line = col / BG;
+  long nlines;
+  size_t base;
+  uint32_t stride;
+  if (MODE == kXFwd || MODE == kXInv) {
+    nlines = (long)gd.K2 * gd.K3;
+    base = (size_t)line * gd.XS * BG + b;
+    stride = BG;
+  } else if (MODE == kYFwd || MODE == kYInv) {
+    nlines = (long)gd.K3 * gd.KX;
+    const long z = line / gd.KX, kx = line % gd.KX;
+    base = ((size_t)z * gd.K2 * gd.XS + 2 * kx) * BG + b;
+    stride = (uint32_t)gd.XS * BG;
+  } else {
+    nlines = (long)gd.K2 * gd.KX;
+    const long y = line / gd.KX, kx = line % gd.KX;
+    base = ((size_t)y * gd.XS + 2 * kx) * BG + b;
+    stride = (uint32_t)(gd.K2 * gd.XS) * BG;
+  }
+  // Both lanes of a pair see the same column, so they leave together (the
+  // shuffles below stay within active pairs).
+  if (line >= nlines) return;
+  // Wave-uniform base pointer plus a small per-lane 32-bit offset, so that the
+  // per-element addresses are one scalar product plus one vector add.
+  const size_t wbase = (size_t)__builtin_amdgcn_readfirstlane((unsigned)(base >> 32)) << 32 |
+                       (size_t)(unsigned)__builtin_amdgcn_readfirstlane((unsigned)base);
+  float* gw = g + wbase;
+  const uint32_t lo = (uint32_t)(base - wbase);
+  float xr[H], xi[H];
+  if (MODE == kXFwd) {
+#pragma unroll
+    for (int m = 0; m < H; ++m) {
+      xr[m] = gw[lo + (uint32_t)(2 * m + h) * stride];
+      xi[m] = 0.f;
+    }
+  } else if (MODE == kXInv) {
+#pragma unroll
+    for (int m = 0; m < H; ++m) {
+      const int n = 2 * m + h;
+      const int kk = n <= H ? n : K - n;
+      const float vr = gw[lo + (uint32_t)(2 * kk) * stride];
+      const float vi = gw[lo + (uint32_t)(2 * kk + 1) * stride];
+      xr[m] = vr;
+      xi[m] = n <= H ? vi : -vi;
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < H; ++m) {
+      const uint32_t o = lo + (uint32_t)(2 * m + h) * stride;
+      xr[m] = gw[o];
+      xi[m] = gw[o + BG];
+    }
+  }
+  constexpr bool FWD = (MODE == kXFwd || MODE == kYFwd || MODE == kZConv);
+  reg_stages<H, 0, FWD>(xr, xi);
+  pair_dit<K, FWD>(xr, xi, h);
+  if (MODE == kZConv) {
+    // natural halves: lane h holds X[h H + k]
+    const long y = line / gd.KX, kx = line % gd.KX;
+    const float* Gl = G + (size_t)y * gd.KX + kx;
+    const uint32_t gstride = (uint32_t)gd.K2 * gd.KX;
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const float w = Gl[(uint32_t)(h * H + k) * gstride];
+      xr[k] *= w;
+      xi[k] *= w;
+    }
+    pair_dif<K, false>(xr, xi, h);
+    reg_stages<H, 0, false>(xr, xi);
+    // decimated output: lane h holds x[2k + h]
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const uint32_t o = lo + (uint32_t)(2 * k + h) * stride;
+      gw[o] = xr[k];
+      gw[o + BG] = xi[k];
+    }
+    return;
+  }
+  if (MODE == kXFwd) {
+    if (h == 0) {
+#pragma unroll
+      for (int k = 0; k < H; ++k) {
+        gw[lo + (uint32_t)(2 * k) * stride] = xr[k];
+        gw[lo + (uint32_t)(2 * k + 1) * stride] = xi[k];
+      }
+    } else {
+      gw[lo + (uint32_t)(2 * H) * stride] = xr[0];
+      gw[lo + (uint32_t)(2 * H + 1) * stride] = xi[0];
+    }
+  } else if (MODE == kXInv) {
+#pragma unroll
+    for (int k = 0; k < H; ++k) gw[lo + (uint32_t)(h * H + k) * stride] = xr[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const uint32_t o = lo + (uint32_t)(h * H + k) * stride;
+      gw[o] = xr[k];
+      gw[o + BG] = xi[k];
+    }
+  }
+}
+
+#define MBD_REG_SIZES(X) \
+  X(8) X(10) X(12) X(16) X(18) X(20) X(24) X(30) X(32) X(36) X(40) X(48) X(50) X(54) \
+  X(60) X(64) X(72) X(80) X(90) X(96) X(100) X(108) X(120) X(128)
+
 #define MBD_FFT_SIZES(X) \
   X(8) X(10) X(12) X(16) X(18) X(20) X(24) X(30) X(32) X(36) X(40) X(48) X(50) X(54) \
   X(60) X(64) X(72) X(80) X(90) X(96) X(100) X(108) X(120) X(128)
@@ -268,6 +510,21 @@ void launch_pass(int K, R* grid, const GridDims& gd, int nchunks, const R* twc, 
   else if (MODE == kYFwd || MODE == kYInv) nlines = (long)gd.K3 * gd.KX;
   else nlines = (long)gd.K2 * gd.KX;
   const long cols = nlines * gd.BG;
+  if constexpr (sizeof(R) == 4) {
+    if (gd.BG >= 16) {
+      dim3 g2((unsigned)((cols + 31) / 32), nchunks);
+      switch (K) {
+#define MBD_REG(KK)                                                                    \
+        case KK:                                                                       \
+          k_fft_reg<KK, MODE><<<g2, 64, 0, st>>>((float*)grid, gd, (const float*)G);   \
+          return;
+        MBD_REG_SIZES(MBD_REG)
+#undef MBD_REG
+        default:
+          break;
+      }
+    }
+  }
   dim3 grd((unsigned)((cols + NC - 1) / NC), nchunks);
   const size_t shm = 2 * (size_t)K * NC * sizeof(R);
   switch (K) {

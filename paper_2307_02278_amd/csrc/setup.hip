@@ -128,13 +128,13 @@ __global__ void k_sorted_tables(Geometry geo, const int* __restrict__ perm,
     }
   }
   // tiles touched by the stencil k = base - t, t = 0..P-1 (mod K), per axis
-  int tl[3][3], nt[3];
+  int tl[3][4], nt[3];
   for (int a = 0; a < 3; ++a) {
     nt[a] = 0;
     for (int k = 0; k < P; ++k) {
       int kk = base[3 * s + a] - k;
       if (kk < 0) kk += geo.K[a];
-      int tt = kk / kSpreadTile;
+      int tt = kk / geo.tile[a];
       bool seen = false;
       for (int q = 0; q < nt[a]; ++q) seen |= (tl[a][q] == tt);
       if (!seen) tl[a][nt[a]++] = tt;
@@ -154,13 +154,13 @@ __global__ void k_tile_fill(Geometry geo, const int* __restrict__ base,
                             int* __restrict__ tile_atoms) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= geo.n) return;
-  int tl[3][3], nt[3];
+  int tl[3][4], nt[3];
   for (int a = 0; a < 3; ++a) {
     nt[a] = 0;
     for (int k = 0; k < P; ++k) {
       int kk = base[3 * s + a] - k;
       if (kk < 0) kk += geo.K[a];
-      int tt = kk / kSpreadTile;
+      int tt = kk / geo.tile[a];
       bool seen = false;
       for (int q = 0; q < nt[a]; ++q) seen |= (tl[a][q] == tt);
       if (!seen) tl[a][nt[a]++] = tt;

@@ -3,20 +3,37 @@
 // Spread: D(k) = sum_j sum_a d_ja dW_j(k)/dR_a with W_j(k) = prod_a M_p(u_ja - k_a),
 // stencil k_a = base_a - t_a (t_a = 0..p-1, periodic wrap). The derivative table
 // dth already carries the K_a / L_a chain-rule factor (orthorhombic cells).
-// One work-group owns an 8x8x8 tile of grid points for one chunk of BG right-hand
-// sides, accumulates every atom whose stencil reaches the tile in LDS, then writes
-// the tile once (no global atomics, no clearing pass).
+// One wavefront owns a 4x4x4 tile of grid points for one chunk of BG right-hand
+// sides, accumulates in registers every atom whose stencil reaches the tile, in a
+// fixed order, and writes the tile once: no atomics, no clearing pass, and a
+// deterministic sum. With one lane per right-hand side the atom's indices and
+// spline weights are wave-uniform.
 //
 // Gather + epilogue: E_rec,i = sum_k grad_i W_i(k) phi(k) (eq. spme), then the
 // generalized field E* = E_dir + E_rec + E_self and
 //   l~ = Omega w + Diag(g) E*      (eq. lk3, in double precision)
-// together with per-block partial sums of w . l~ for a_k (eq. recurs2).
+// with per-block partial sums of w . l~ for a_k (eq. recurs2). Again one wavefront
+// per atom and one lane per right-hand side.
 #include "common.h"
 
 namespace mbd {
 
 namespace {
 
+// Lanes of a wavefront: BG right-hand sides x NSUB sub-lanes that share the stencil.
+template <int BG>
+struct Lanes {
+  static constexpr int NSUB = 64 / BG;
+};
+
+// Spread with register tiles: one wavefront owns a 4x4x4 tile of grid points for BG
+// right-hand sides and keeps the 64 point values of its lane in registers
+// (64 / NSUB per lane when fewer than 64 right-hand sides share the wavefront).
+// It walks the tile's atom list in a fixed order, so the result is deterministic.
+// For one atom the weights along each axis of the tile are uniform scalars:
+//   w_a(q) = M_p(u_a - k_a) for the tile point k_a = tile origin + q,
+// nonzero only when 0 <= t = (base_a - k_a) mod K_a < p, i.e. t = o_a - q with
+// o_a = (base_a - origin_a) mod K_a.
 template <typename R, int P, int BG>
 __global__ void __launch_bounds__(256)
 k_spread(const Geometry geo, const int* __restrict__ tile_start,
@@ -24,60 +41,84 @@ k_spread(const Geometry geo, const int* __restrict__ tile_start,
          const R* __restrict__ th, const R* __restrict__ dth, const R* __restrict__ dv, int B,
          R* __restrict__ grid, size_t chunk_elems) {
   constexpr int T = kSpreadTile;
-  __shared__ R acc[T * T * T * BG];
-  const int tile = blockIdx.x;
+  constexpr int NSUB = Lanes<BG>::NSUB;
+  constexpr int NP = T * T * T / NSUB;  // points per lane
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int ntiles = geo.tiles[0] * geo.tiles[1] * geo.tiles[2];
+  const int tile = blockIdx.x * 4 + wave;
+  if (tile >= ntiles) return;
   const int chunk = blockIdx.y;
+  const int b = lane % BG;
+  const int sub = lane / BG;
+  const int bg = chunk * BG + b;
   const int tx = tile % geo.tiles[0];
   const int ty = (tile / geo.tiles[0]) % geo.tiles[1];
   const int tz = tile / (geo.tiles[0] * geo.tiles[1]);
   const int x0 = tx * T, y0 = ty * T, z0 = tz * T;
-  for (int i = threadIdx.x; i < T * T * T * BG; i += blockDim.x) acc[i] = R(0);
-  __syncthreads();
-  const int lo = tile_start[tile], hi = tile_start[tile + 1];
-  const int items = (hi - lo) * P * P * BG;
   const int K1 = geo.K[0], K2 = geo.K[1], K3 = geo.K[2];
-  for (int it = threadIdx.x; it < items; it += blockDim.x) {
-    const int b = it % BG;
-    const int rest = it / BG;
-    const int row = rest % (P * P);
-    const int a = rest / (P * P);
-    const int t2 = row / P, t3 = row % P;
-    const int s = tile_atoms[lo + a];
-    int k2 = base[3 * s + 1] - t2;
-    if (k2 < 0) k2 += K2;
-    int k3 = base[3 * s + 2] - t3;
-    if (k3 < 0) k3 += K3;
-    const int ly = k2 - y0, lz = k3 - z0;
-    if (ly < 0 || ly >= T || lz < 0 || lz >= T) continue;
-    const int bg = chunk * BG + b;
+  R acc[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) acc[i] = R(0);
+  const int lo = tile_start[tile], hi = tile_start[tile + 1];
+  for (int a = lo; a < hi; ++a) {
+    const int s = __builtin_amdgcn_readfirstlane(tile_atoms[a]);
+    int ox = __builtin_amdgcn_readfirstlane(base[3 * s]) - x0;
+    int oy = __builtin_amdgcn_readfirstlane(base[3 * s + 1]) - y0;
+    int oz = __builtin_amdgcn_readfirstlane(base[3 * s + 2]) - z0;
+    if (ox < 0) ox += K1;
+    if (oy < 0) oy += K2;
+    if (oz < 0) oz += K3;
+    const R* thp = th + s * 3 * P;
+    const R* dthp = dth + s * 3 * P;
+    R wx[T], dwx[T], wy[T], dwy[T], wz[T], dwz[T];
+#pragma unroll
+    for (int q = 0; q < T; ++q) {
+      const int t1 = ox - q, t2 = oy - q, t3 = oz - q;
+      const bool v1 = t1 >= 0 && t1 < P, v2 = t2 >= 0 && t2 < P, v3 = t3 >= 0 && t3 < P;
+      wx[q] = v1 ? thp[t1] : R(0);
+      dwx[q] = v1 ? dthp[t1] : R(0);
+      wy[q] = v2 ? thp[P + t2] : R(0);
+      dwy[q] = v2 ? dthp[P + t2] : R(0);
+      wz[q] = v3 ? thp[2 * P + t3] : R(0);
+      dwz[q] = v3 ? dthp[2 * P + t3] : R(0);
+    }
     const R d0 = dv[(s * 3 + 0) * B + bg];
     const R d1 = dv[(s * 3 + 1) * B + bg];
     const R d2 = dv[(s * 3 + 2) * B + bg];
-    const R* thp = th + s * 3 * P;
-    const R* dthp = dth + s * 3 * P;
-    const R m1 = thp[P + t2], dm1 = dthp[P + t2];
-    const R m2 = thp[2 * P + t3], dm2 = dthp[2 * P + t3];
-    const R A = d0 * m1 * m2;
-    const R Bc = d1 * dm1 * m2 + d2 * m1 * dm2;
-    const int bx = base[3 * s + 0];
+    if (NSUB == 1) {
+      // uniform point loop: skip rows and points outside the atom's stencil
 #pragma unroll
-    for (int t1 = 0; t1 < P; ++t1) {
-      int k1 = bx - t1;
-      if (k1 < 0) k1 += K1;
-      const int lx = k1 - x0;
-      if (lx < 0 || lx >= T) continue;
-      const R v = dthp[t1] * A + thp[t1] * Bc;
-      atomicAdd(&acc[((lz * T + ly) * T + lx) * BG + b], v);
+      for (int pz = 0; pz < T; ++pz) {
+        if (oz - pz < 0 || oz - pz >= P) continue;
+#pragma unroll
+        for (int py = 0; py < T; ++py) {
+          if (oy - py < 0 || oy - py >= P) continue;
+          const R A = d0 * wy[py] * wz[pz];
+          const R Bc = d1 * dwy[py] * wz[pz] + d2 * wy[py] * dwz[pz];
+#pragma unroll
+          for (int px = 0; px < T; ++px) {
+            if (ox - px < 0 || ox - px >= P) continue;
+            acc[(pz * T + py) * T + px] += dwx[px] * A + wx[px] * Bc;
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        const int p = sub + i * NSUB;
+        const int px = p % T, py = (p / T) % T, pz = p / (T * T);
+        acc[i] += (dwx[px] * wy[py] * wz[pz]) * d0 + (wx[px] * dwy[py] * wz[pz]) * d1 +
+                  (wx[px] * wy[py] * dwz[pz]) * d2;
+      }
     }
   }
-  __syncthreads();
   R* g = grid + (size_t)chunk * chunk_elems;
   const int XS = K1 + 2;
-  for (int i = threadIdx.x; i < T * T * T * BG; i += blockDim.x) {
-    const int b = i % BG;
-    const int pt = i / BG;
-    const int lx = pt % T, ly = (pt / T) % T, lz = pt / (T * T);
-    const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    const int p = sub + i * NSUB;
+    const int x = x0 + p % T, y = y0 + (p / T) % T, z = z0 + p / (T * T);
     if (x < K1 && y < K2 && z < K3) g[(((size_t)z * K2 + y) * XS + x) * BG + b] = acc[i];
   }
 }
@@ -90,73 +131,103 @@ k_gather_epilogue(const Geometry geo, const int* __restrict__ base, const R* __r
                   const double* __restrict__ g, const double* __restrict__ om2, int B,
                   uint32_t comps, double self_coef, double* __restrict__ lt,
                   double* __restrict__ part) {
-  constexpr int ROWS = 256 / BG;
+  constexpr int NSUB = Lanes<BG>::NSUB;
   __shared__ double red[256];
-  const int b = threadIdx.x % BG;
-  const int row = threadIdx.x / BG;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int b = lane % BG;
+  const int sub = lane / BG;
   const int chunk = blockIdx.y;
   const int bg = chunk * BG + b;
   const R* gr = grid + (size_t)chunk * chunk_elems;
   const int K1 = geo.K[0], K2 = geo.K[1], K3 = geo.K[2];
   const int XS = K1 + 2;
   double dot = 0.0;
-  for (int s = blockIdx.x * ROWS + row; s < geo.n; s += gridDim.x * ROWS) {
+  // Blocks are dealt round-robin to the 8 XCDs; give each XCD one contiguous
+  // (spatially compact) range of sorted atoms so that its L2 holds their stencils.
+  const int nb8 = gridDim.x / 8;
+  const int lblock = (blockIdx.x % 8) * nb8 + blockIdx.x / 8;
+  const int nw = gridDim.x * 4;
+  const int wid = lblock * 4 + wave;
+  const int s_lo = (int)(((long)geo.n * wid) / nw);
+  const int s_hi = (int)(((long)geo.n * (wid + 1)) / nw);
+  for (int s = s_lo; s < s_hi; ++s) {
     R e0 = R(0), e1 = R(0), e2 = R(0);
     if (comps & MBD_C_REC) {
       const R* thp = th + s * 3 * P;
       const R* dthp = dth + s * 3 * P;
+      R mx[P], dmx[P], my[P], dmy[P], mz[P], dmz[P];
+#pragma unroll
+      for (int t = 0; t < P; ++t) {
+        mx[t] = thp[t]; dmx[t] = dthp[t];
+        my[t] = thp[P + t]; dmy[t] = dthp[P + t];
+        mz[t] = thp[2 * P + t]; dmz[t] = dthp[2 * P + t];
+      }
       const int bx = base[3 * s], by = base[3 * s + 1], bz = base[3 * s + 2];
-#pragma unroll 1
+      int kxs[P];
+#pragma unroll
+      for (int t1 = 0; t1 < P; ++t1) {
+        int k1 = bx - t1;
+        if (k1 < 0) k1 += K1;
+        kxs[t1] = k1 * BG + b;
+      }
+#pragma unroll
       for (int t3 = 0; t3 < P; ++t3) {
         int k3 = bz - t3;
         if (k3 < 0) k3 += K3;
-        const R m3 = thp[2 * P + t3], dm3 = dthp[2 * P + t3];
-#pragma unroll 1
+#pragma unroll
         for (int t2 = 0; t2 < P; ++t2) {
+          if ((t3 * P + t2) % NSUB != sub) continue;
           int k2 = by - t2;
           if (k2 < 0) k2 += K2;
-          const R m2 = thp[P + t2], dm2 = dthp[P + t2];
-          const R* line = gr + ((size_t)k3 * K2 + k2) * XS * BG + b;
+          const R* line = gr + ((size_t)k3 * K2 + k2) * XS * BG;
           R sx = R(0), sy = R(0);
 #pragma unroll
           for (int t1 = 0; t1 < P; ++t1) {
-            int k1 = bx - t1;
-            if (k1 < 0) k1 += K1;
-            const R phi = line[(size_t)k1 * BG];
-            sx += dthp[t1] * phi;
-            sy += thp[t1] * phi;
+            const R phi = line[kxs[t1]];
+            sx += dmx[t1] * phi;
+            sy += mx[t1] * phi;
           }
-          e0 += sx * m2 * m3;
-          e1 += sy * dm2 * m3;
-          e2 += sy * m2 * dm3;
+          e0 += sx * my[t2] * mz[t3];
+          e1 += sy * dmy[t2] * mz[t3];
+          e2 += sy * my[t2] * dmz[t3];
         }
       }
-    }
-    const double gs = g[s];
-    const double o2 = om2[s];
+      // combine the sub-lanes that split the stencil rows
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const size_t idx = ((size_t)s * 3 + a) * B + bg;
-      const double wv = w[idx];
-      double E = (a == 0) ? (double)e0 : (a == 1) ? (double)e1 : (double)e2;
-      if (comps & MBD_C_DIR) E += (double)Ed[idx];
-      if (comps & MBD_C_SELF) E += self_coef * gs * wv;
-      double l = gs * E;
-      if (comps & MBD_C_DIAG) l += o2 * wv;
-      lt[idx] = l;
-      dot += wv * l;
+      for (int off = BG; off < 64; off <<= 1) {
+        e0 += __shfl_xor(e0, off);
+        e1 += __shfl_xor(e1, off);
+        e2 += __shfl_xor(e2, off);
+      }
+    }
+    if (sub == 0) {
+      const double gs = g[s];
+      const double o2 = om2[s];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const size_t idx = ((size_t)s * 3 + a) * B + bg;
+        const double wv = w[idx];
+        double E = (a == 0) ? (double)e0 : (a == 1) ? (double)e1 : (double)e2;
+        if (comps & MBD_C_DIR) E += (double)Ed[idx];
+        if (comps & MBD_C_SELF) E += self_coef * gs * wv;
+        double l = gs * E;
+        if (comps & MBD_C_DIAG) l += o2 * wv;
+        lt[idx] = l;
+        dot += wv * l;
+      }
     }
   }
+  // per-RHS sum over the four wavefronts (sub-lanes hold zero)
   red[threadIdx.x] = dot;
   __syncthreads();
-  for (int h = ROWS / 2; h > 0; h >>= 1) {
-    if (row < h) red[threadIdx.x] += red[threadIdx.x + h * BG];
-    __syncthreads();
+  if (threadIdx.x < BG) {
+    double t = 0.0;
+    for (int wv = 0; wv < 4; ++wv)
+      for (int sb = 0; sb < NSUB; ++sb) t += red[wv * 64 + sb * BG + threadIdx.x];
+    part[((size_t)blockIdx.x * 4 + 0) * B + chunk * BG + threadIdx.x] = t;
   }
-  if (row == 0) part[((size_t)blockIdx.x * 4 + 0) * B + bg] = red[threadIdx.x];
 }
-
-inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 }  // namespace
 
@@ -164,9 +235,9 @@ template <typename R>
 void launch_spread(const Geometry& geo, const SysBuffers& b, int B, int BG, hipStream_t st) {
   const size_t chunk = (size_t)geo.K[2] * geo.K[1] * (geo.K[0] + 2) * BG;
   const int ntiles = geo.tiles[0] * geo.tiles[1] * geo.tiles[2];
-  dim3 grd(ntiles, B / BG);
-#define MBD_SPREAD(PP, BB)                                                                   \
-  k_spread<R, PP, BB><<<grd, 256, 0, st>>>(geo, b.tile_start, b.tile_atoms, b.base,         \
+  dim3 grd((ntiles + 3) / 4, B / BG);
+#define MBD_SPREAD(PP, BB)                                                                  \
+  k_spread<R, PP, BB><<<grd, 256, 0, st>>>(geo, b.tile_start, b.tile_atoms, b.base,        \
                                            (const R*)b.th, (const R*)b.dth, (const R*)b.dv, \
                                            B, (R*)b.grid, chunk)
 #define MBD_SPREAD_P(BB)                    \
@@ -181,9 +252,8 @@ void launch_spread(const Geometry& geo, const SysBuffers& b, int B, int BG, hipS
     case 4: MBD_SPREAD_P(4); break;
     case 8: MBD_SPREAD_P(8); break;
     case 16: MBD_SPREAD_P(16); break;
-    case 32:
-      if constexpr (sizeof(R) == 4) { MBD_SPREAD_P(32); }
-      break;
+    case 32: MBD_SPREAD_P(32); break;
+    case 64: MBD_SPREAD_P(64); break;
   }
 #undef MBD_SPREAD_P
 #undef MBD_SPREAD
@@ -212,6 +282,7 @@ void launch_epilogue(const Geometry& geo, const SysBuffers& b, const double* w, 
     case 8: MBD_GATHER_P(8); break;
     case 16: MBD_GATHER_P(16); break;
     case 32: MBD_GATHER_P(32); break;
+    case 64: MBD_GATHER_P(64); break;
   }
 #undef MBD_GATHER_P
 #undef MBD_GATHER
