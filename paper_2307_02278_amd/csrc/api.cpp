@@ -124,9 +124,10 @@ void allocate_system(Plan& plan, System& S, int R_probes, int m) {
   SysBuffers& b = S.buf;
   size_t& by = S.bytes;
   const int n = g.n, B = plan.B;
-  const int ncell = g.nc[0] * g.nc[1] * g.nc[2];
+  const int ncell = cell_slots(g);
   const int ntiles = g.tiles[0] * g.tiles[1] * g.tiles[2];
   b.perm = dalloc<int>(plan, n, by);
+  b.subkey = dalloc<uint32_t>(plan, n, by);
   b.cell_of = dalloc<int>(plan, n, by);
   b.cell_start = dalloc<int>(plan, ncell + 1, by);
   b.cell_cursor = dalloc<int>(plan, ncell, by);
@@ -183,24 +184,50 @@ template <typename R>
 void run_setup(Plan& plan, System& S, const double* pos) {
   staged(plan, MBD_STAGE_SETUP, [&] {
     launch_setup<R>(S.geo, S.buf, pos, S.src.alpha, S.src.omega, S.src.r_vdw, plan.stream);
+    if (S.buf.pg_T) launch_pair_build<R>(S.geo, S.buf, false, plan.stream);
   });
 }
 
+// Size and build the direct-space tensor list (B >= 16) for the positions set up
+// last: one counting pass, then a capacity of 1.25 x the largest group plus 32
+// (room for later set_positions calls), then the build.
+template <typename R>
+void create_pair_list(Plan& plan, System& S) {
+  SysBuffers& b = S.buf;
+  const int ngroups = (S.geo.n + kGroup - 1) / kGroup;
+  b.pg_count = dalloc<int>(plan, ngroups, S.bytes);
+  b.pg_max = dalloc<int>(plan, 1, S.bytes);
+  launch_pair_build<R>(S.geo, b, true, plan.stream);
+  check(hipGetLastError(), "pair list count");
+  int mx = 0;
+  check(hipStreamSynchronize(plan.stream), "pair list count");
+  check(hipMemcpy(&mx, b.pg_max, sizeof(int), hipMemcpyDeviceToHost), "pair list count");
+  b.pg_cap = ((mx + mx / 4 + 32) + 15) / 16 * 16;
+  b.pg_hdr = dalloc<int2>(plan, (size_t)ngroups * b.pg_cap, S.bytes);
+  b.pg_T = dalloc<R>(plan, (size_t)ngroups * b.pg_cap * kCandStride, S.bytes);
+  launch_pair_build<R>(S.geo, b, false, plan.stream);
+}
+
 // One application of C to the block stored at w (internal layout), into Lt.
+// The grid stages run chunk by chunk (BG right-hand sides at a time) so that one
+// chunk's grid stays resident in the last-level cache between the passes.
 template <typename R>
 void matvec_block(Plan& plan, System& S, const double* w, uint32_t comps) {
   const hipStream_t st = plan.stream;
+  const int nch = plan.B / plan.BG;
   if (comps & MBD_C_DIR)
     staged(plan, MBD_STAGE_PAIR, [&] { launch_pair<R>(S.geo, S.buf, plan.B, st); });
-  if (comps & MBD_C_REC) {
-    staged(plan, MBD_STAGE_SPREAD,
-           [&] { launch_spread<R>(S.geo, S.buf, plan.B, plan.BG, st); });
-    for (int pass = 0; pass < 5; ++pass)
-      staged(plan, MBD_STAGE_FFT_X + pass,
-             [&] { launch_fft_pass<R>(S.geo, S.buf, plan.B, plan.BG, pass, st); });
+  for (int c = 0; c < nch; ++c) {
+    if (comps & MBD_C_REC) {
+      staged(plan, MBD_STAGE_SPREAD,
+             [&] { launch_spread<R>(S.geo, S.buf, plan.B, plan.BG, c, 1, st); });
+      for (int pass = 0; pass < 5; ++pass)
+        staged(plan, MBD_STAGE_FFT_X + pass,
+               [&] { launch_fft_pass<R>(S.geo, S.buf, plan.B, plan.BG, c, 1, pass, st); });
+    }
+    staged(plan, MBD_STAGE_GATHER,
+           [&] { launch_epilogue<R>(S.geo, S.buf, w, plan.B, plan.BG, c, 1, comps, st); });
   }
-  staged(plan, MBD_STAGE_GATHER,
-         [&] { launch_epilogue<R>(S.geo, S.buf, w, plan.B, plan.BG, comps, st); });
 }
 
 template <typename R>
@@ -412,18 +439,22 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
         rp = std::max(rp, smax * (1.0 + std::log(1.0 / tol - 1.0) / prm.damp_d));
       }
       g.r_pair = rp;
+      g.mbits = 0;
       for (int a = 0; a < 3; ++a) {
         g.nc[a] = std::max(1, (int)std::floor(g.L[a] / (0.5 * rp)));
         g.nc[a] = std::min(g.nc[a], 64);
         g.hc[a] = g.L[a] / g.nc[a];
         g.nr[a] = (int)std::ceil(rp / g.hc[a] - 1e-12);
+        while ((1 << g.mbits) < g.nc[a]) ++g.mbits;
       }
       if (plan.prec == MBD_PREC_FP64) {
         allocate_system<double>(plan, S, prm.n_probes, prm.n_steps);
         run_setup<double>(plan, S, sy.pos);
+        if (plan.B >= 16) create_pair_list<double>(plan, S);
       } else {
         allocate_system<float>(plan, S, prm.n_probes, prm.n_steps);
         run_setup<float>(plan, S, sy.pos);
+        if (plan.B >= 16) create_pair_list<float>(plan, S);
       }
       check(hipGetLastError(), "setup launch");
     }
@@ -528,6 +559,15 @@ mbd_status mbd_check(mbd_plan plan) {
     return fail(MBD_E_HIP, "stream synchronize failed");
   if (hipMemcpy(&st, P.status, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess)
     return fail(MBD_E_HIP, "status read failed");
+  for (const auto& S : P.sys) {
+    if (!S.buf.pg_max) continue;
+    int mx = 0;
+    if (hipMemcpy(&mx, S.buf.pg_max, sizeof(mx), hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(MBD_E_HIP, "status read failed");
+    if (mx > S.buf.pg_cap)
+      return fail(MBD_E_STATE, "direct-space tensor list overflow: the positions moved too far "
+                               "from those the plan was created with; create a new plan");
+  }
   if (st & mbd::kErrNotPosdef) return fail(MBD_E_NOT_POSDEF, "a Ritz value is <= 0");
   if (st & (mbd::kErrNonfinite | mbd::kErrNoConverge))
     return fail(MBD_E_NONFINITE, "non-finite value or non-converged tridiagonal");

@@ -16,6 +16,11 @@ constexpr int kMaxOrder = 8;
 constexpr int kRedBlocks = 1024;   // blocks (and partial sums) of the row reductions
 constexpr int kSpreadTile = 4;     // grid points per spread-tile edge (one wavefront per tile)
 constexpr int kMaxSteps = 512;
+// Direct-space tensor list: targets per group, stored components per (source,
+// target) pair (xx, yy, zz, xy, xz, yz) and values per listed source.
+constexpr int kGroup = 16;
+constexpr int kTensorWords = 6;
+constexpr int kCandStride = kGroup * kTensorWords;
 
 // Device-side error bits (status word).
 enum : uint32_t { kErrNotPosdef = 1u, kErrNonfinite = 2u, kErrNoConverge = 4u };
@@ -31,24 +36,55 @@ struct Geometry {
   int nc[3];             // cells per axis
   double hc[3];          // cell edge per axis
   int nr[3];             // neighbour-cell range per axis
+  int mbits;             // bits per axis of the Morton cell index
   int tile[3];           // spread tile edge per axis (grid points)
   int tiles[3];          // spread tiles per axis
   double beta, damp_d;
 };
+
+// Cells are numbered along a Morton (Z-order) curve so that consecutive sorted
+// atoms stay spatially compact; cell_start has 2^(3 mbits) + 1 entries.
+__host__ __device__ inline uint32_t morton_spread(uint32_t v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+__host__ __device__ inline uint32_t morton_compact(uint32_t v) {
+  v &= 0x09249249u;
+  v = (v ^ (v >> 2)) & 0x030C30C3u;
+  v = (v ^ (v >> 4)) & 0x0300F00Fu;
+  v = (v ^ (v >> 8)) & 0x030000FFu;
+  v = (v ^ (v >> 16)) & 0x000003FFu;
+  return v;
+}
+__host__ __device__ inline int cell_index(int cx, int cy, int cz) {
+  return (int)(morton_spread((uint32_t)cx) | (morton_spread((uint32_t)cy) << 1) |
+               (morton_spread((uint32_t)cz) << 2));
+}
+__host__ __device__ inline void cell_coords(int c, int& cx, int& cy, int& cz) {
+  cx = (int)morton_compact((uint32_t)c);
+  cy = (int)morton_compact((uint32_t)c >> 1);
+  cz = (int)morton_compact((uint32_t)c >> 2);
+}
+inline int cell_slots(const Geometry& g) { return 1 << (3 * g.mbits); }
 
 // Device buffers of one system.
 struct SysBuffers {
   // sorted atom data
   int* perm = nullptr;         // [n] sorted -> caller index
   int* cell_of = nullptr;      // [n] cell of each caller atom
-  int* cell_start = nullptr;   // [ncell + 1]
-  int* cell_cursor = nullptr;  // [ncell]
+  int* cell_start = nullptr;   // [cell_slots + 1], Morton-indexed
+  int* cell_cursor = nullptr;  // [cell_slots]
+  uint32_t* subkey = nullptr;  // [n] Morton code of the atom's sub-cell (order inside a cell)
   double* wpos = nullptr;      // [n][3] wrapped positions, caller order
   void* loc = nullptr;         // Real [n][4] cell-local position + damping radius (sorted)
   double* g = nullptr;         // [n] omega sqrt(alpha) (sorted)
   double* om2 = nullptr;       // [n] omega^2 (sorted)
   int* base = nullptr;         // [n][3] spline base indices (sorted)
-  int* scell = nullptr;        // [n] cell of each sorted atom
+  int* scell = nullptr;        // [n] Morton cell index of each sorted atom
   void* th = nullptr;          // Real [n][3][p] M_p(w + t)
   void* dth = nullptr;         // Real [n][3][p] (K_a / L_a) M_p'(w + t)
   int* tile_count = nullptr;   // [ntiles + 1]
@@ -56,6 +92,12 @@ struct SysBuffers {
   int* tile_atoms = nullptr;   // [n * max tiles per stencil]
   void* G = nullptr;           // Real [K3][K2][K1/2 + 1]
   void* tw = nullptr;          // Real [2][K1 + K2 + K3] twiddles exp(-2 pi i j / K_a)
+  // direct-space tensor list (B >= 16): groups of kGroup sorted targets
+  int pg_cap = 0;              // listed sources per group (capacity)
+  int* pg_count = nullptr;     // [ngroups] listed sources (may exceed pg_cap: overflow)
+  int* pg_max = nullptr;       // [1] max over groups of pg_count
+  int2* pg_hdr = nullptr;      // [ngroups][pg_cap] (source index, 16-bit target mask)
+  void* pg_T = nullptr;        // Real [ngroups][pg_cap][kGroup][kTensorWords]
   // Lanczos state for one block of right-hand sides
   double* W = nullptr;         // [m][n][3][B] Krylov vectors, unnormalized
   double* Lt = nullptr;        // [n][3][B] C w_k
@@ -114,20 +156,24 @@ template <typename R>
 void launch_pair(const Geometry& g, const SysBuffers& b, int B, hipStream_t st);
 
 template <typename R>
+void launch_pair_build(const Geometry& g, const SysBuffers& b, bool count_only, hipStream_t st);
+
+template <typename R>
 long long count_pairs(const Geometry& g, const SysBuffers& b, hipStream_t st);
 
 template <typename R>
-void launch_spread(const Geometry& g, const SysBuffers& b, int B, int BG, hipStream_t st);
+void launch_spread(const Geometry& g, const SysBuffers& b, int B, int BG, int chunk0, int nchunks,
+                   hipStream_t st);
 
 template <typename R>
-void launch_fft_pass(const Geometry& g, const SysBuffers& b, int B, int BG, int pass,
-                     hipStream_t st);
+void launch_fft_pass(const Geometry& g, const SysBuffers& b, int B, int BG, int chunk0,
+                     int nchunks, int pass, hipStream_t st);
 
 void fill_int(int* p, int v, int n, hipStream_t st);
 
 template <typename R>
 void launch_epilogue(const Geometry& g, const SysBuffers& b, const double* w, int B, int BG,
-                     uint32_t comps, hipStream_t st);
+                     int chunk0, int nchunks, uint32_t comps, hipStream_t st);
 
 void launch_probes(const Geometry& g, const SysBuffers& b, int B, int nb, int probe0,
                    uint64_t seed, int system, bool use_float, hipStream_t st);

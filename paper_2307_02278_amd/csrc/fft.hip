@@ -152,6 +152,7 @@ enum Pass { kXFwd = 0, kYFwd = 1, kZConv = 2, kYInv = 3, kXInv = 4 };
 struct GridDims {
   int K1, K2, K3, XS, KX, BG;
   size_t chunk_elems;
+  int chunk0;
 };
 
 template <typename R, int K, int NC, int P, int MODE>
@@ -163,7 +164,7 @@ k_fft(R* __restrict__ grid, GridDims gd, const R* __restrict__ twc,
   R* im = re + K * NC;
   const int c = threadIdx.x % NC;
   const int q = threadIdx.x / NC;
-  R* g = grid + (size_t)blockIdx.y * gd.chunk_elems;
+  R* g = grid + (size_t)(blockIdx.y + gd.chunk0) * gd.chunk_elems;
   const long col = (long)blockIdx.x * NC + c;
   const int BG = gd.BG;
   const int b = (int)(col % BG);
@@ -382,7 +383,7 @@ template <int K, int MODE>
 __global__ void __launch_bounds__(64)
 k_fft_reg(float* __restrict__ grid, GridDims gd, const float* __restrict__ G) {
   constexpr int H = K / 2;
-  float* g = grid + (size_t)blockIdx.y * gd.chunk_elems;
+  float* g = grid + (size_t)(blockIdx.y + gd.chunk0) * gd.chunk_elems;
   const int h = threadIdx.x & 1;
   const long col = (long)blockIdx.x * 32 + (threadIdx.x >> 1);
   const int BG = gd.BG;
@@ -554,8 +555,8 @@ bool fft_supported(int k) {
 // One pass (0 forward x, 1 forward y, 2 z with convolution, 3 inverse y, 4 inverse x)
 // over every grid chunk.
 template <typename R>
-void launch_fft_pass(const Geometry& geo, const SysBuffers& b, int B, int BG, int pass,
-                     hipStream_t st) {
+void launch_fft_pass(const Geometry& geo, const SysBuffers& b, int B, int BG, int chunk0,
+                     int nchunks, int pass, hipStream_t st) {
   GridDims gd;
   gd.K1 = geo.K[0];
   gd.K2 = geo.K[1];
@@ -564,7 +565,8 @@ void launch_fft_pass(const Geometry& geo, const SysBuffers& b, int B, int BG, in
   gd.KX = geo.K[0] / 2 + 1;
   gd.BG = BG;
   gd.chunk_elems = (size_t)gd.K3 * gd.K2 * gd.XS * BG;
-  const int nchunks = B / BG;
+  gd.chunk0 = chunk0;
+  (void)B;
   R* grid = (R*)b.grid;
   const R* tw = (const R*)b.tw;
   const int Ksum = geo.K[0] + geo.K[1] + geo.K[2];
@@ -581,9 +583,9 @@ void launch_fft_pass(const Geometry& geo, const SysBuffers& b, int B, int BG, in
   }
 }
 
-template void launch_fft_pass<float>(const Geometry&, const SysBuffers&, int, int, int,
+template void launch_fft_pass<float>(const Geometry&, const SysBuffers&, int, int, int, int, int,
                                      hipStream_t);
-template void launch_fft_pass<double>(const Geometry&, const SysBuffers&, int, int, int,
+template void launch_fft_pass<double>(const Geometry&, const SysBuffers&, int, int, int, int, int,
                                       hipStream_t);
 
 }  // namespace mbd

@@ -9,11 +9,17 @@
 // exceeds half the box.
 //
 // Two variants:
-//  - direct: one thread per target atom, all right-hand sides (B <= 8) in registers;
-//  - tiled:  a work-group per (target cell, group of BP right-hand sides). Phase 1
-//    evaluates the tensor for up to 256 (target, source) candidates, one per lane,
-//    into LDS; phase 2 has one lane per right-hand side and applies the stored
-//    3x3 tensors of the valid pairs to the source dipoles.
+//  - direct: one thread per target atom, all right-hand sides (B <= 8) in
+//    registers, tensors evaluated on the fly;
+//  - list:   for B >= 16. The positions do not change during a Lanczos run, so
+//    the tensors are evaluated once per device setup (k_pair_build) and kept in
+//    device memory, grouped by 16 consecutive sorted target atoms: for every
+//    source image within r_pair of at least one target of the group, a header
+//    (source, 16-bit target mask) and the 6 independent components of T_dir for
+//    each of the 16 targets (zero where the pair is out of range). Each matvec
+//    (k_pair_list) streams a group's tensors through LDS once and applies them to
+//    all right-hand sides, one lane per right-hand side, so every source dipole
+//    load serves all of the group's targets within range.
 #include "common.h"
 #include "mbd_math.h"
 
@@ -29,7 +35,8 @@ k_pair_direct(const Geometry geo, const int* __restrict__ cell_start,
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= geo.n) return;
   const int c = scell[s];
-  const int cx = c % geo.nc[0], cy = (c / geo.nc[0]) % geo.nc[1], cz = c / (geo.nc[0] * geo.nc[1]);
+  int cx, cy, cz;
+  cell_coords(c, cx, cy, cz);
   const R xi = loc[4 * s], yi = loc[4 * s + 1], zi = loc[4 * s + 2], si = loc[4 * s + 3];
   const R tau = (R)geo.tau, dd = (R)geo.damp_d;
   const R rp2 = (R)(geo.r_pair * geo.r_pair);
@@ -49,7 +56,7 @@ k_pair_direct(const Geometry geo, const int* __restrict__ cell_start,
         if (wx < 0) wx += geo.nc[0];
         const R sx = (R)(ox * geo.hc[0]);
         const bool zero = (ox == 0 && oy == 0 && oz == 0);
-        const int cc = (wz * geo.nc[1] + wy) * geo.nc[0] + wx;
+        const int cc = cell_index(wx, wy, wz);
         const int j0 = cell_start[cc], j1 = cell_start[cc + 1];
         for (int j = j0; j < j1; ++j) {
           if (zero && j == s) continue;
@@ -85,93 +92,208 @@ k_pair_direct(const Geometry geo, const int* __restrict__ cell_start,
   }
 }
 
-template <typename R, int BP>
+
+// ---------------------------------------------------------------------------
+// Tensor list: build (once per device setup) and apply (every matvec).
+// ---------------------------------------------------------------------------
+
+// One wavefront per group of kGroup consecutive sorted targets. Candidate sources
+// are the atoms of the cells around the group whose distance to the group's
+// bounding box is below r_pair; those within r_pair of at least one target are
+// appended (wavefront ballot, fixed order) with their tensors. With cap == 0 only
+// the counts are produced (plan sizing).
+template <typename R>
 __global__ void __launch_bounds__(256)
-k_pair_tiled(const Geometry geo, const int* __restrict__ cell_start, const R* __restrict__ loc,
-             const R* __restrict__ dv, R* __restrict__ Ed, int B) {
-  constexpr int NT = 256 / BP;  // targets per pass
-  constexpr int NS = BP;        // sources per batch
-  __shared__ R Tt[NT][NS][6];
-  __shared__ unsigned char ok[NT][NS];
-  const int c = blockIdx.x;
-  const int rhs = blockIdx.y * BP + (threadIdx.x % BP);
-  const int ti = threadIdx.x / BP;  // phase-2 target slot
-  const int pt = threadIdx.x / NS;  // phase-1 target slot
-  const int ps = threadIdx.x % NS;  // phase-1 source slot
-  const int cx = c % geo.nc[0], cy = (c / geo.nc[0]) % geo.nc[1], cz = c / (geo.nc[0] * geo.nc[1]);
-  const int i0 = cell_start[c], i1 = cell_start[c + 1];
+k_pair_build(const Geometry geo, const int* __restrict__ cell_start,
+             const int* __restrict__ scell, const R* __restrict__ loc, int cap,
+             int2* __restrict__ hdr, R* __restrict__ Tg, int* __restrict__ gcount,
+             int* __restrict__ maxcount) {
+  __shared__ R tgt_all[4][kGroup][4];
+  __shared__ int tcell_all[4][kGroup][3];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int group = blockIdx.x * 4 + wave;
+  const int g0 = group * kGroup;
+  if (g0 >= geo.n) return;
+  const int n = geo.n;
+  const int nc0 = geo.nc[0], nc1 = geo.nc[1], nc2 = geo.nc[2];
+  const R h0 = (R)geo.hc[0], h1 = (R)geo.hc[1], h2 = (R)geo.hc[2];
+  R(*tgt)[4] = tgt_all[wave];
+  int(*tcell)[3] = tcell_all[wave];
+
+  // targets relative to the cell of the group's first atom
+  const int ti = g0 + (lane & 15);
+  const bool tvalid = ti < n;
+  int c0x, c0y, c0z, tcx, tcy, tcz;
+  cell_coords(scell[g0], c0x, c0y, c0z);
+  cell_coords(scell[tvalid ? ti : g0], tcx, tcy, tcz);
+  const int dcx = tcx - c0x, dcy = tcy - c0y, dcz = tcz - c0z;
+  const R* tl = loc + 4 * (size_t)(tvalid ? ti : g0);
+  const R tx = tl[0] + dcx * h0, ty = tl[1] + dcy * h1, tz = tl[2] + dcz * h2;
+  if (lane < kGroup) {
+    tgt[lane][0] = tx; tgt[lane][1] = ty; tgt[lane][2] = tz; tgt[lane][3] = tl[3];
+    tcell[lane][0] = dcx; tcell[lane][1] = dcy; tcell[lane][2] = dcz;
+  }
+  // bounding box of the valid targets and their cell-offset range
+  R bx0 = tx, bx1 = tx, by0 = ty, by1 = ty, bz0 = tz, bz1 = tz;
+  int mx0 = dcx, mx1 = dcx, my0 = dcy, my1 = dcy, mz0 = dcz, mz1 = dcz;
+  for (int off = 1; off < 16; off <<= 1) {
+    bx0 = min(bx0, __shfl_xor(bx0, off)); bx1 = max(bx1, __shfl_xor(bx1, off));
+    by0 = min(by0, __shfl_xor(by0, off)); by1 = max(by1, __shfl_xor(by1, off));
+    bz0 = min(bz0, __shfl_xor(bz0, off)); bz1 = max(bz1, __shfl_xor(bz1, off));
+    mx0 = min(mx0, __shfl_xor(mx0, off)); mx1 = max(mx1, __shfl_xor(mx1, off));
+    my0 = min(my0, __shfl_xor(my0, off)); my1 = max(my1, __shfl_xor(my1, off));
+    mz0 = min(mz0, __shfl_xor(mz0, off)); mz1 = max(mz1, __shfl_xor(mz1, off));
+  }
+  // all lanes now agree (every lane reduced over the same 16 target copies)
+  __builtin_amdgcn_wave_barrier();
+  const int ntg = min(kGroup, n - g0);
   const R tau = (R)geo.tau, dd = (R)geo.damp_d;
   const R rp2 = (R)(geo.r_pair * geo.r_pair);
-  for (int tg = i0; tg < i1; tg += NT) {
-    const int ia = tg + pt;  // phase-1 target atom
-    R xi = R(0), yi = R(0), zi = R(0), si = R(0);
-    if (ia < i1) {
-      xi = loc[4 * ia]; yi = loc[4 * ia + 1]; zi = loc[4 * ia + 2]; si = loc[4 * ia + 3];
-    }
-    R e0 = R(0), e1 = R(0), e2 = R(0);
-    for (int oz = -geo.nr[2]; oz <= geo.nr[2]; ++oz) {
-      int wz = (cz + oz) % geo.nc[2];
-      if (wz < 0) wz += geo.nc[2];
-      const R sz = (R)(oz * geo.hc[2]);
-      for (int oy = -geo.nr[1]; oy <= geo.nr[1]; ++oy) {
-        int wy = (cy + oy) % geo.nc[1];
-        if (wy < 0) wy += geo.nc[1];
-        const R sy = (R)(oy * geo.hc[1]);
-        for (int ox = -geo.nr[0]; ox <= geo.nr[0]; ++ox) {
-          int wx = (cx + ox) % geo.nc[0];
-          if (wx < 0) wx += geo.nc[0];
-          const R sx = (R)(ox * geo.hc[0]);
-          const bool zero = (ox == 0 && oy == 0 && oz == 0);
-          const int cc = (wz * geo.nc[1] + wy) * geo.nc[0] + wx;
-          const int j0 = cell_start[cc], j1 = cell_start[cc + 1];
-          for (int sb = j0; sb < j1; sb += NS) {
-            // phase 1: one candidate pair per lane
-            {
-              const int j = sb + ps;
-              bool v = (ia < i1) && (j < j1) && !(zero && j == ia);
-              R A = R(0), Bk = R(0), rx = R(0), ry = R(0), rz = R(0);
-              if (v) {
-                rx = loc[4 * j] - xi + sx;
-                ry = loc[4 * j + 1] - yi + sy;
-                rz = loc[4 * j + 2] - zi + sz;
-                const R r2 = rx * rx + ry * ry + rz * rz;
-                v = r2 < rp2;
-                if (v) direct_kernel<R>(r2, tau, R(1) / (loc[4 * j + 3] + si), dd, A, Bk);
-              }
-              ok[pt][ps] = v ? 1 : 0;
-              Tt[pt][ps][0] = A - Bk * rx * rx;
-              Tt[pt][ps][1] = A - Bk * ry * ry;
-              Tt[pt][ps][2] = A - Bk * rz * rz;
-              Tt[pt][ps][3] = -Bk * rx * ry;
-              Tt[pt][ps][4] = -Bk * rx * rz;
-              Tt[pt][ps][5] = -Bk * ry * rz;
-            }
-            __syncthreads();
-            // phase 2: one lane per right-hand side
-            if (rhs < B) {
-              const int ns = min(NS, j1 - sb);
-              for (int q = 0; q < ns; ++q) {
-                if (!ok[ti][q]) continue;
-                const int j = sb + q;
-                const R d0 = dv[(j * 3 + 0) * B + rhs];
-                const R d1 = dv[(j * 3 + 1) * B + rhs];
-                const R d2 = dv[(j * 3 + 2) * B + rhs];
-                const R* T = Tt[ti][q];
-                e0 += T[0] * d0 + T[3] * d1 + T[4] * d2;
-                e1 += T[3] * d0 + T[1] * d1 + T[5] * d2;
-                e2 += T[4] * d0 + T[5] * d1 + T[2] * d2;
+  int count = 0;
+  for (int dz = mz0 - geo.nr[2]; dz <= mz1 + geo.nr[2]; ++dz) {
+    int wz = (c0z + dz) % nc2;
+    if (wz < 0) wz += nc2;
+    for (int dy = my0 - geo.nr[1]; dy <= my1 + geo.nr[1]; ++dy) {
+      int wy = (c0y + dy) % nc1;
+      if (wy < 0) wy += nc1;
+      for (int dx = mx0 - geo.nr[0]; dx <= mx1 + geo.nr[0]; ++dx) {
+        int wx = (c0x + dx) % nc0;
+        if (wx < 0) wx += nc0;
+        const int cc = cell_index(wx, wy, wz);
+        const int j0 = cell_start[cc], j1 = cell_start[cc + 1];
+        const R sx = dx * h0, sy = dy * h1, sz = dz * h2;
+        for (int jb = j0; jb < j1; jb += 64) {
+          const int j = jb + lane;
+          uint32_t mask = 0;
+          R px = R(0), py = R(0), pz = R(0), ps = R(0);
+          if (j < j1) {
+            px = loc[4 * (size_t)j] + sx;
+            py = loc[4 * (size_t)j + 1] + sy;
+            pz = loc[4 * (size_t)j + 2] + sz;
+            ps = loc[4 * (size_t)j + 3];
+            const R ex = max(max(bx0 - px, px - bx1), R(0));
+            const R ey = max(max(by0 - py, py - by1), R(0));
+            const R ez = max(max(bz0 - pz, pz - bz1), R(0));
+            if (ex * ex + ey * ey + ez * ez < rp2) {
+              for (int t = 0; t < ntg; ++t) {
+                const R rx = px - tgt[t][0], ry = py - tgt[t][1], rz = pz - tgt[t][2];
+                const bool self = (j == g0 + t) && dx == tcell[t][0] && dy == tcell[t][1] &&
+                                  dz == tcell[t][2];
+                if (!self && rx * rx + ry * ry + rz * rz < rp2) mask |= 1u << t;
               }
             }
-            __syncthreads();
           }
+          const unsigned long long bal = __ballot(mask != 0u);
+          const int nk = __popcll(bal);
+          if (nk == 0) continue;
+          const int slot = count + (int)__builtin_amdgcn_mbcnt_hi(
+                                       (unsigned)(bal >> 32),
+                                       __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+          if (mask != 0u && slot < cap) {
+            const size_t e = (size_t)group * cap + slot;
+            hdr[e] = make_int2(j, (int)mask);
+            R* T = Tg + e * kCandStride;
+            for (int t = 0; t < kGroup; ++t) {
+              R A = R(0), Bk = R(0), rx = R(0), ry = R(0), rz = R(0);
+              if ((mask >> t) & 1u) {
+                rx = px - tgt[t][0]; ry = py - tgt[t][1]; rz = pz - tgt[t][2];
+                direct_kernel<R>(rx * rx + ry * ry + rz * rz, tau, R(1) / (ps + tgt[t][3]), dd,
+                                 A, Bk);
+              }
+              R* o = T + t * kTensorWords;
+              o[0] = A - Bk * rx * rx;
+              o[1] = A - Bk * ry * ry;
+              o[2] = A - Bk * rz * rz;
+              o[3] = -Bk * rx * ry;
+              o[4] = -Bk * rx * rz;
+              o[5] = -Bk * ry * rz;
+            }
+          }
+          count += nk;
         }
       }
     }
-    const int it = tg + ti;
-    if (it < i1 && rhs < B) {
-      Ed[(it * 3 + 0) * B + rhs] = e0;
-      Ed[(it * 3 + 1) * B + rhs] = e1;
-      Ed[(it * 3 + 2) * B + rhs] = e2;
+  }
+  if (lane == 0) {
+    gcount[group] = count;
+    atomicMax(maxcount, count);
+  }
+}
+
+// E_dir of one group per work-group: WPB wavefronts, one lane per right-hand
+// side (B = 64 WPB), or for B = 16, 32 one wavefront whose lanes split into
+// NSUB = 64 / B target subsets. Tensors of CH candidates at a time are staged in
+// LDS; the wave-uniform target mask skips out-of-range (target, source) pairs.
+template <typename R, int NSUB, int WPB>
+__global__ void __launch_bounds__(64 * WPB)
+k_pair_list(const Geometry geo, const int2* __restrict__ hdr, const R* __restrict__ Tg,
+            const int* __restrict__ gcount, int cap, const R* __restrict__ dv,
+            R* __restrict__ Ed, int B) {
+  constexpr int NT = 64 * WPB;
+  constexpr int CH = 16 * WPB;        // candidates per LDS chunk
+  constexpr int KT = kGroup / NSUB;   // target slots per lane
+  constexpr int BW = 64 / NSUB;       // right-hand sides per wavefront
+  constexpr int W16 = (int)(kCandStride * sizeof(R) / 16);  // 16-byte words per candidate
+  __shared__ uint4 Tl4[CH * W16];
+  __shared__ int2 hl[CH];
+  const R* Tl = reinterpret_cast<const R*>(Tl4);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int rhs = (tid >> 6) * 64 + lane % BW;
+  const int sub = lane / BW;
+  // XCD-aware: contiguous ranges of groups per XCD (blocks are dealt round-robin)
+  const int per = (gridDim.x + 7) / 8;
+  const int group = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int ngroups = (geo.n + kGroup - 1) / kGroup;
+  if (group >= ngroups) return;  // uniform over the work-group
+  const int cnt = min(gcount[group], cap);
+  const int2* H = hdr + (size_t)group * cap;
+  const uint4* T4 = reinterpret_cast<const uint4*>(Tg + (size_t)group * cap * kCandStride);
+
+  R acc[KT][3];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) acc[k][0] = acc[k][1] = acc[k][2] = R(0);
+
+  for (int c0 = 0; c0 < cnt; c0 += CH) {
+    const int nc = min(CH, cnt - c0);
+    __syncthreads();
+    for (int w = tid; w < nc * W16; w += NT) Tl4[w] = T4[(size_t)c0 * W16 + w];
+    if (tid < nc) hl[tid] = H[c0 + tid];
+    __syncthreads();
+    int2 h = hl[0];
+    int j = __builtin_amdgcn_readfirstlane(h.x);
+    const R* dj = dv + (size_t)j * 3 * B + rhs;
+    R n0 = dj[0], n1 = dj[B], n2 = dj[2 * B];
+    for (int c = 0; c < nc; ++c) {
+      const uint32_t msk = (uint32_t)__builtin_amdgcn_readfirstlane(h.y);
+      const R d0 = n0, d1 = n1, d2 = n2;
+      if (c + 1 < nc) {  // next candidate's dipoles while this one is applied
+        h = hl[c + 1];
+        j = __builtin_amdgcn_readfirstlane(h.x);
+        dj = dv + (size_t)j * 3 * B + rhs;
+        n0 = dj[0]; n1 = dj[B]; n2 = dj[2 * B];
+      }
+      const R* Tc = Tl + c * kCandStride + sub * kTensorWords;
+#pragma unroll
+      for (int k = 0; k < KT; ++k) {
+        if ((msk >> (k * NSUB)) & ((1u << NSUB) - 1u)) {
+          const R* t = Tc + k * NSUB * kTensorWords;
+          const R txx = t[0], tyy = t[1], tzz = t[2], txy = t[3], txz = t[4], tyz = t[5];
+          acc[k][0] += txx * d0 + txy * d1 + txz * d2;
+          acc[k][1] += txy * d0 + tyy * d1 + tyz * d2;
+          acc[k][2] += txz * d0 + tyz * d1 + tzz * d2;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const int i = group * kGroup + k * NSUB + sub;
+    if (i < geo.n) {
+      Ed[((size_t)i * 3 + 0) * B + rhs] = acc[k][0];
+      Ed[((size_t)i * 3 + 1) * B + rhs] = acc[k][1];
+      Ed[((size_t)i * 3 + 2) * B + rhs] = acc[k][2];
     }
   }
 }
@@ -183,7 +305,8 @@ __global__ void k_count_pairs(const Geometry geo, const int* __restrict__ cell_s
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= geo.n) return;
   const int c = scell[s];
-  const int cx = c % geo.nc[0], cy = (c / geo.nc[0]) % geo.nc[1], cz = c / (geo.nc[0] * geo.nc[1]);
+  int cx, cy, cz;
+  cell_coords(c, cx, cy, cz);
   const R xi = loc[4 * s], yi = loc[4 * s + 1], zi = loc[4 * s + 2];
   const R rp2 = (R)(geo.r_pair * geo.r_pair);
   unsigned long long cnt = 0;
@@ -194,7 +317,7 @@ __global__ void k_count_pairs(const Geometry geo, const int* __restrict__ cell_s
       for (int ox = -geo.nr[0]; ox <= geo.nr[0]; ++ox) {
         int wx = ((cx + ox) % geo.nc[0] + geo.nc[0]) % geo.nc[0];
         const bool zero = (ox == 0 && oy == 0 && oz == 0);
-        const int cc = (wz * geo.nc[1] + wy) * geo.nc[0] + wx;
+        const int cc = cell_index(wx, wy, wz);
         for (int j = cell_start[cc]; j < cell_start[cc + 1]; ++j) {
           if (zero && j == s) continue;
           const R rx = loc[4 * j] - xi + (R)(ox * geo.hc[0]);
@@ -242,20 +365,32 @@ void launch_pair(const Geometry& g, const SysBuffers& b, int B, hipStream_t st) 
     }
     return;
   }
-  const int ncell = g.nc[0] * g.nc[1] * g.nc[2];
-  if (B >= 64) {
-    dim3 grd(ncell, (B + 63) / 64);
-    k_pair_tiled<R, 64><<<grd, 256, 0, st>>>(g, b.cell_start, loc, dv, Ed, B);
-  } else if (B >= 32) {
-    dim3 grd(ncell, (B + 31) / 32);
-    k_pair_tiled<R, 32><<<grd, 256, 0, st>>>(g, b.cell_start, loc, dv, Ed, B);
-  } else {
-    dim3 grd(ncell, (B + 15) / 16);
-    k_pair_tiled<R, 16><<<grd, 256, 0, st>>>(g, b.cell_start, loc, dv, Ed, B);
+  // a multiple of 8 work-groups, so that the XCD remap covers every group
+  const int ngroups = (g.n + kGroup - 1) / kGroup;
+  const int nblk = (ngroups + 7) / 8 * 8;
+  const int2* H = b.pg_hdr;
+  const R* T = (const R*)b.pg_T;
+  switch (B) {
+    case 16: k_pair_list<R, 4, 1><<<nblk, 64, 0, st>>>(g, H, T, b.pg_count, b.pg_cap, dv, Ed, B); break;
+    case 32: k_pair_list<R, 2, 1><<<nblk, 64, 0, st>>>(g, H, T, b.pg_count, b.pg_cap, dv, Ed, B); break;
+    case 64: k_pair_list<R, 1, 1><<<nblk, 64, 0, st>>>(g, H, T, b.pg_count, b.pg_cap, dv, Ed, B); break;
+    case 128: k_pair_list<R, 1, 2><<<nblk, 128, 0, st>>>(g, H, T, b.pg_count, b.pg_cap, dv, Ed, B); break;
+    default: k_pair_list<R, 1, 4><<<nblk, 256, 0, st>>>(g, H, T, b.pg_count, b.pg_cap, dv, Ed, B); break;
   }
+}
+
+template <typename R>
+void launch_pair_build(const Geometry& g, const SysBuffers& b, bool count_only, hipStream_t st) {
+  const int ngroups = (g.n + kGroup - 1) / kGroup;
+  fill_int(b.pg_max, 0, 1, st);
+  k_pair_build<R><<<(ngroups + 3) / 4, 256, 0, st>>>(
+      g, b.cell_start, b.scell, (const R*)b.loc, count_only ? 0 : b.pg_cap, b.pg_hdr,
+      (R*)b.pg_T, b.pg_count, b.pg_max);
 }
 
 template void launch_pair<float>(const Geometry&, const SysBuffers&, int, hipStream_t);
 template void launch_pair<double>(const Geometry&, const SysBuffers&, int, hipStream_t);
+template void launch_pair_build<float>(const Geometry&, const SysBuffers&, bool, hipStream_t);
+template void launch_pair_build<double>(const Geometry&, const SysBuffers&, bool, hipStream_t);
 
 }  // namespace mbd

@@ -13,13 +13,13 @@ namespace {
 __global__ void k_wrap_count(int n, const double* __restrict__ pos, double L0, double L1,
                              double L2, int nc0, int nc1, int nc2, double h0, double h1,
                              double h2, double* __restrict__ wpos, int* __restrict__ cell_of,
-                             int* __restrict__ count) {
+                             uint32_t* __restrict__ subkey, int* __restrict__ count) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double L[3] = {L0, L1, L2};
   const double h[3] = {h0, h1, h2};
   const int nc[3] = {nc0, nc1, nc2};
-  int c[3];
+  int c[3], f[3];
   for (int a = 0; a < 3; ++a) {
     double x = pos[3 * i + a];
     x -= L[a] * floor(x / L[a]);
@@ -28,9 +28,13 @@ __global__ void k_wrap_count(int n, const double* __restrict__ pos, double L0, d
     wpos[3 * i + a] = x;
     int ci = (int)(x / h[a]);
     c[a] = ci >= nc[a] ? nc[a] - 1 : ci;
+    // 4 sub-cells per axis order the atoms inside the cell
+    int fi = (int)((x - c[a] * h[a]) / h[a] * 4.0);
+    f[a] = fi < 0 ? 0 : (fi > 3 ? 3 : fi);
   }
-  int cell = (c[2] * nc[1] + c[1]) * nc[0] + c[0];
+  int cell = cell_index(c[0], c[1], c[2]);
   cell_of[i] = cell;
+  subkey[i] = (uint32_t)cell_index(f[0], f[1], f[2]);
   atomicAdd(&count[cell], 1);
 }
 
@@ -71,15 +75,17 @@ __global__ void k_scatter(int n, const int* __restrict__ cell_of, const int* __r
   perm[start[c] + slot] = i;
 }
 
-// Make the order inside each cell deterministic: ascending caller index.
-__global__ void k_sort_cells(int ncell, const int* __restrict__ start, int* __restrict__ perm) {
+// Deterministic order inside each cell: by sub-cell (Morton), then caller index.
+__global__ void k_sort_cells(int ncell, const int* __restrict__ start,
+                             const uint32_t* __restrict__ subkey, int* __restrict__ perm) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncell) return;
   int lo = start[c], hi = start[c + 1];
   for (int i = lo + 1; i < hi; ++i) {
-    int v = perm[i];
+    const int v = perm[i];
+    const unsigned long long kv = ((unsigned long long)subkey[v] << 32) | (unsigned)v;
     int j = i - 1;
-    while (j >= lo && perm[j] > v) {
+    while (j >= lo && (((unsigned long long)subkey[perm[j]] << 32) | (unsigned)perm[j]) > kv) {
       perm[j + 1] = perm[j];
       --j;
     }
@@ -106,7 +112,7 @@ __global__ void k_sorted_tables(Geometry geo, const int* __restrict__ perm,
     c[a] = ci >= geo.nc[a] ? geo.nc[a] - 1 : ci;
   }
   for (int a = 0; a < 3; ++a) loc[4 * s + a] = (R)(x[a] - c[a] * geo.hc[a]);
-  scell[s] = (c[2] * geo.nc[1] + c[1]) * geo.nc[0] + c[0];
+  scell[s] = cell_index(c[0], c[1], c[2]);
   loc[4 * s + 3] = (R)(geo.beta * rvdw[i]);
   g[s] = omega[i] * sqrt(alpha[i]);
   om2[s] = omega[i] * omega[i];
@@ -208,17 +214,17 @@ void fill_int(int* p, int v, int n, hipStream_t st) {
 template <typename R>
 void launch_setup(const Geometry& g, SysBuffers& b, const double* pos, const double* alpha,
                   const double* omega, const double* rvdw, hipStream_t st) {
-  const int ncell = g.nc[0] * g.nc[1] * g.nc[2];
+  const int ncell = cell_slots(g);
   const int ntiles = g.tiles[0] * g.tiles[1] * g.tiles[2];
   fill_int(b.cell_cursor, 0, ncell, st);
   k_wrap_count<<<blocks_for(g.n, 256), 256, 0, st>>>(
       g.n, pos, g.L[0], g.L[1], g.L[2], g.nc[0], g.nc[1], g.nc[2], g.hc[0], g.hc[1], g.hc[2],
-      b.wpos, b.cell_of, b.cell_cursor);
+      b.wpos, b.cell_of, b.subkey, b.cell_cursor);
   k_scan<<<1, 1024, 0, st>>>(ncell, b.cell_cursor, b.cell_start);
   fill_int(b.cell_cursor, 0, ncell, st);
   k_scatter<<<blocks_for(g.n, 256), 256, 0, st>>>(g.n, b.cell_of, b.cell_start, b.cell_cursor,
                                                    b.perm);
-  k_sort_cells<<<blocks_for(ncell, 128), 128, 0, st>>>(ncell, b.cell_start, b.perm);
+  k_sort_cells<<<blocks_for(ncell, 128), 128, 0, st>>>(ncell, b.cell_start, b.subkey, b.perm);
   fill_int(b.tile_count, 0, ntiles + 1, st);
 #define MBD_TABLES(PP)                                                                        \
   k_sorted_tables<R, PP><<<blocks_for(g.n, 128), 128, 0, st>>>(                               \

@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(256)
 k_spread(const Geometry geo, const int* __restrict__ tile_start,
          const int* __restrict__ tile_atoms, const int* __restrict__ base,
          const R* __restrict__ th, const R* __restrict__ dth, const R* __restrict__ dv, int B,
-         R* __restrict__ grid, size_t chunk_elems) {
+         R* __restrict__ grid, size_t chunk_elems, int chunk0) {
   constexpr int T = kSpreadTile;
   constexpr int NSUB = Lanes<BG>::NSUB;
   constexpr int NP = T * T * T / NSUB;  // points per lane
@@ -48,7 +48,7 @@ k_spread(const Geometry geo, const int* __restrict__ tile_start,
   const int ntiles = geo.tiles[0] * geo.tiles[1] * geo.tiles[2];
   const int tile = blockIdx.x * 4 + wave;
   if (tile >= ntiles) return;
-  const int chunk = blockIdx.y;
+  const int chunk = blockIdx.y + chunk0;
   const int b = lane % BG;
   const int sub = lane / BG;
   const int bg = chunk * BG + b;
@@ -130,14 +130,14 @@ k_gather_epilogue(const Geometry geo, const int* __restrict__ base, const R* __r
                   const R* __restrict__ Ed, const double* __restrict__ w,
                   const double* __restrict__ g, const double* __restrict__ om2, int B,
                   uint32_t comps, double self_coef, double* __restrict__ lt,
-                  double* __restrict__ part) {
+                  double* __restrict__ part, int chunk0) {
   constexpr int NSUB = Lanes<BG>::NSUB;
   __shared__ double red[256];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int b = lane % BG;
   const int sub = lane / BG;
-  const int chunk = blockIdx.y;
+  const int chunk = blockIdx.y + chunk0;
   const int bg = chunk * BG + b;
   const R* gr = grid + (size_t)chunk * chunk_elems;
   const int K1 = geo.K[0], K2 = geo.K[1], K3 = geo.K[2];
@@ -232,14 +232,15 @@ k_gather_epilogue(const Geometry geo, const int* __restrict__ base, const R* __r
 }  // namespace
 
 template <typename R>
-void launch_spread(const Geometry& geo, const SysBuffers& b, int B, int BG, hipStream_t st) {
+void launch_spread(const Geometry& geo, const SysBuffers& b, int B, int BG, int chunk0,
+                   int nchunks, hipStream_t st) {
   const size_t chunk = (size_t)geo.K[2] * geo.K[1] * (geo.K[0] + 2) * BG;
   const int ntiles = geo.tiles[0] * geo.tiles[1] * geo.tiles[2];
-  dim3 grd((ntiles + 3) / 4, B / BG);
+  dim3 grd((ntiles + 3) / 4, nchunks);
 #define MBD_SPREAD(PP, BB)                                                                  \
   k_spread<R, PP, BB><<<grd, 256, 0, st>>>(geo, b.tile_start, b.tile_atoms, b.base,        \
                                            (const R*)b.th, (const R*)b.dth, (const R*)b.dv, \
-                                           B, (R*)b.grid, chunk)
+                                           B, (R*)b.grid, chunk, chunk0)
 #define MBD_SPREAD_P(BB)                    \
   switch (geo.p) {                          \
     case 4: MBD_SPREAD(4, BB); break;       \
@@ -261,14 +262,14 @@ void launch_spread(const Geometry& geo, const SysBuffers& b, int B, int BG, hipS
 
 template <typename R>
 void launch_epilogue(const Geometry& geo, const SysBuffers& b, const double* w, int B, int BG,
-                     uint32_t comps, hipStream_t st) {
+                     int chunk0, int nchunks, uint32_t comps, hipStream_t st) {
   const size_t chunk = (size_t)geo.K[2] * geo.K[1] * (geo.K[0] + 2) * BG;
-  dim3 grd(kRedBlocks, B / BG);
+  dim3 grd(kRedBlocks, nchunks);
   const double self_coef = -4.0 * geo.tau * geo.tau * geo.tau / (3.0 * sqrt(M_PI));
 #define MBD_GATHER(PP, BB)                                                                  \
   k_gather_epilogue<R, PP, BB><<<grd, 256, 0, st>>>(                                       \
       geo, b.base, (const R*)b.th, (const R*)b.dth, (const R*)b.grid, chunk,               \
-      (const R*)b.Ed, w, b.g, b.om2, B, comps, self_coef, b.Lt, b.part)
+      (const R*)b.Ed, w, b.g, b.om2, B, comps, self_coef, b.Lt, b.part, chunk0)
 #define MBD_GATHER_P(BB)                    \
   switch (geo.p) {                          \
     case 4: MBD_GATHER(4, BB); break;       \
@@ -288,11 +289,13 @@ void launch_epilogue(const Geometry& geo, const SysBuffers& b, const double* w, 
 #undef MBD_GATHER
 }
 
-template void launch_spread<float>(const Geometry&, const SysBuffers&, int, int, hipStream_t);
-template void launch_spread<double>(const Geometry&, const SysBuffers&, int, int, hipStream_t);
+template void launch_spread<float>(const Geometry&, const SysBuffers&, int, int, int, int,
+                                   hipStream_t);
+template void launch_spread<double>(const Geometry&, const SysBuffers&, int, int, int, int,
+                                    hipStream_t);
 template void launch_epilogue<float>(const Geometry&, const SysBuffers&, const double*, int, int,
-                                     uint32_t, hipStream_t);
+                                     int, int, uint32_t, hipStream_t);
 template void launch_epilogue<double>(const Geometry&, const SysBuffers&, const double*, int, int,
-                                      uint32_t, hipStream_t);
+                                      int, int, uint32_t, hipStream_t);
 
 }  // namespace mbd

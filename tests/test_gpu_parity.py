@@ -88,6 +88,41 @@ def test_matvec_block_layouts_agree(tiny, block):
     assert _rel(got, want) < 1e-11
 
 
+@pytest.mark.parametrize("block", [16, 32, 64, 128, 256])
+@pytest.mark.parametrize("comp", [2, 15])
+def test_matvec_mixed_wide_blocks(tiny, block, comp):
+    """Float32 paths used for many right-hand sides (tensor-list pair kernel with 1, 2 or 4
+    target subsets per wavefront and 1, 2 or 4 wavefronts per group, register FFT, 64-wide
+    grid chunks) against the oracle; r_pair > L/2 exercises several images."""
+    import paper_2307_02278_amd as P
+    plan, _ = _plan(tiny, P.PREC_MIXED, block, grid=(16, 16, 16), tau_ang=0.35, rc_ang=13.0)
+    op = _oracle_op(tiny, plan)
+    g = torch.Generator().manual_seed(100 + block)
+    v = torch.randn(block, tiny.n, 3, dtype=torch.float64, generator=g)
+    got = plan.matvec(v.cuda(), components=comp).cpu()
+    want = op(v.permute(1, 2, 0), comp).permute(2, 0, 1)
+    assert _rel(got, want) < (2e-6 if comp == 15 else 1e-5)
+
+
+@pytest.fixture(scope="module")
+def water3k():
+    return synth.workload("medium").systems[0]
+
+
+@pytest.mark.parametrize("prec,block,tol", [(0, 2, 1e-11), (1, 64, 2e-6)])
+def test_matvec_water_3000(water3k, prec, block, tol):
+    """Medium water box (K=48, r_c=7 A): several cells per axis, many tiles and groups."""
+    s = water3k
+    plan, _ = _plan(s, prec, block, grid=(48, 48, 48), rc_ang=7.0)
+    op = _oracle_op(s, plan)
+    n = min(block, 8)
+    g = torch.Generator().manual_seed(7)
+    v = torch.randn(n, s.n, 3, dtype=torch.float64, generator=g)
+    got = plan.matvec(v.cuda()).cpu()
+    want = op(v.permute(1, 2, 0)).permute(2, 0, 1)
+    assert _rel(got, want) < tol
+
+
 def test_matvec_noncubic_grid_radix_3_5():
     """Orthorhombic box, K = (20, 24, 30): radices 4, 2, 3 and 5, unequal axes."""
     import paper_2307_02278_amd as P
@@ -167,3 +202,39 @@ def test_reorthogonalization_modes_agree(tiny):
         plan.check()
     assert es[1] == pytest.approx(es[0], rel=1e-10)
     assert es[2] == pytest.approx(es[0], rel=1e-10)
+
+
+def test_set_positions_rebuilds_pair_list():
+    """Moving the atoms re-runs the device setup, including the direct-space tensor list."""
+    import paper_2307_02278_amd as P
+    s0 = synth.workload("medium").systems[0]
+    plan, _ = _plan(s0, P.PREC_MIXED, 16, grid=(48, 48, 48), rc_ang=7.0)
+    rng = np.random.default_rng(5)
+    pos1 = s0.pos + rng.normal(scale=0.1 * A, size=s0.pos.shape)
+    plan.set_positions(torch.as_tensor(pos1).cuda())
+    s1 = synth.System("moved", pos1, s0.cell, s0.alpha, s0.omega, s0.rvdw)
+    op = _oracle_op(s1, plan)
+    v = torch.randn(3, s1.n, 3, dtype=torch.float64, generator=torch.Generator().manual_seed(9))
+    got = plan.matvec(v.cuda()).cpu()
+    plan.check()
+    assert _rel(got, op(v.permute(1, 2, 0)).permute(2, 0, 1)) < 2e-6
+
+
+def test_pair_list_overflow_is_reported():
+    """Positions far denser than at plan creation overflow the tensor list's capacity: the
+    kernels stay within their buffers and check() reports the condition."""
+    import paper_2307_02278_amd as P
+    rng = np.random.default_rng(11)
+    n, L = 600, 60.0
+    pos0 = rng.uniform(0, L, size=(n, 3)) * A
+    cell = np.eye(3) * L * A
+    ones = np.ones(n)
+    s0 = synth.System("dilute", pos0, cell, 6.0 * ones, 0.5 * ones, 3.5 * ones)
+    plan, _ = _plan(s0, P.PREC_MIXED, 16, grid=(40, 40, 40), rc_ang=6.0)
+    plan.check()
+    pos1 = rng.uniform(0, 4.0, size=(n, 3)) * A
+    plan.set_positions(torch.as_tensor(pos1).cuda())
+    plan.matvec(torch.randn(2, n, 3, dtype=torch.float64).cuda())
+    with pytest.raises(P.MbdError) as ei:
+        plan.check()
+    assert ei.value.code == -9
