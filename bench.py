@@ -56,6 +56,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--plain-probes", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 B=1 leg")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -81,6 +84,15 @@ def main():
     log(f"tau={info.tau:.6f}/bohr r_pair={info.r_pair / A:.3f} A cells={list(info.cells)} "
         f"pairs={n_pairs} workspace={info.workspace_bytes / 2**30:.2f} GiB")
     pos = torch.as_tensor(s.pos, dtype=torch.float64, device="cuda")
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 3 x 1 GiB device-to-device copies")
 
     def step():
         plan.set_positions(pos)
@@ -136,20 +148,22 @@ def main():
     plan.close()
 
     # Plain form: one probe vector at a time in float64, same kernels, same GPU.
-    Rp = args.plain_probes
-    prm_p = P.Params(real_cutoff=wl.real_cutoff_angstrom * A, grid=K, n_probes=Rp, n_steps=m,
-                     block=1, precision=P.PREC_FP64, seed=wl.probe_seed)
-    plain = P.Plan([ds], prm_p)
-    plain.execute()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plain.execute()
-    torch.cuda.synchronize()
-    tp = time.perf_counter() - t0
-    plain.check()
-    plain_rate = Rp * m / tp
-    plain.close()
-    log(f"plain fp64 B=1: {plain_rate:.1f} matvecs/s")
+    plain_rate = None
+    if not args.no_plain:
+        Rp = args.plain_probes
+        prm_p = P.Params(real_cutoff=wl.real_cutoff_angstrom * A, grid=K, n_probes=Rp,
+                         n_steps=m, block=1, precision=P.PREC_FP64, seed=wl.probe_seed)
+        plain = P.Plan([ds], prm_p)
+        plain.execute()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain.execute()
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        plain.check()
+        plain_rate = Rp * m / tp
+        plain.close()
+        log(f"plain fp64 B=1: {plain_rate:.1f} matvecs/s")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -188,8 +202,8 @@ def main():
                    "block": B, "pairs": n_pairs},
         "energy_ms": round(ms_per_step, 3),
         "energy_ha": energy,
-        "plain_matvecs_per_s": round(plain_rate, 2),
-        "speedup_vs_plain": round(value / plain_rate, 2),
+        "plain_matvecs_per_s": round(plain_rate, 2) if plain_rate else None,
+        "speedup_vs_plain": round(value / plain_rate, 2) if plain_rate else None,
         "path_algorithmic_GBps": round(path_gbs, 1),
         "path_roofline_frac": round(path_gbs / HBM_PEAK_GBS, 4),
         "stage_ms_per_step": {k: round(v, 3) for k, v in stage_ms.items()},

@@ -43,10 +43,19 @@ k_spread(const Geometry geo, const int* __restrict__ tile_start,
   constexpr int T = kSpreadTile;
   constexpr int NSUB = Lanes<BG>::NSUB;
   constexpr int NP = T * T * T / NSUB;  // points per lane
+  constexpr int NWT = 6 * T;            // staged weights per atom: w, dw along x, y, z
+  __shared__ R wts_all[4][64][NWT];
+  __shared__ int4 sat_all[4][64];       // atom, stencil offsets (o_x, o_y, o_z)
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
+  R(*wts)[NWT] = wts_all[wave];
+  int4* sat = sat_all[wave];
   const int ntiles = geo.tiles[0] * geo.tiles[1] * geo.tiles[2];
-  const int tile = blockIdx.x * 4 + wave;
+  // Blocks are dealt round-robin to the 8 XCDs (gridDim.x is a multiple of 8):
+  // each XCD takes one contiguous range of tiles, a slab of the grid, so the
+  // dipoles of the atoms it spreads stay in its L2.
+  const int per = gridDim.x / 8;
+  const int tile = ((blockIdx.x % 8) * per + blockIdx.x / 8) * 4 + wave;
   if (tile >= ntiles) return;
   const int chunk = blockIdx.y + chunk0;
   const int b = lane % BG;
@@ -61,57 +70,91 @@ k_spread(const Geometry geo, const int* __restrict__ tile_start,
 #pragma unroll
   for (int i = 0; i < NP; ++i) acc[i] = R(0);
   const int lo = tile_start[tile], hi = tile_start[tile + 1];
-  for (int a = lo; a < hi; ++a) {
-    const int s = __builtin_amdgcn_readfirstlane(tile_atoms[a]);
-    int ox = __builtin_amdgcn_readfirstlane(base[3 * s]) - x0;
-    int oy = __builtin_amdgcn_readfirstlane(base[3 * s + 1]) - y0;
-    int oz = __builtin_amdgcn_readfirstlane(base[3 * s + 2]) - z0;
-    if (ox < 0) ox += K1;
-    if (oy < 0) oy += K2;
-    if (oz < 0) oz += K3;
-    const R* thp = th + s * 3 * P;
-    const R* dthp = dth + s * 3 * P;
-    R wx[T], dwx[T], wy[T], dwy[T], wz[T], dwz[T];
+  for (int a0 = lo; a0 < hi; a0 += 64) {
+    const int na = min(64, hi - a0);
+    // Stage: lane i computes the tile-clipped weights of the batch's atom i.
+    // For one atom the weights along each axis of the tile are
+    //   w_a(q) = M_p(u_a - k_a) at the tile point k_a = origin_a + q,
+    // nonzero only when t = o_a - q lies in [0, p), o_a = (base_a - origin_a) mod K_a.
+    if (lane < na) {
+      const int s = tile_atoms[a0 + lane];
+      int o[3] = {base[3 * s] - x0, base[3 * s + 1] - y0, base[3 * s + 2] - z0};
+      if (o[0] < 0) o[0] += K1;
+      if (o[1] < 0) o[1] += K2;
+      if (o[2] < 0) o[2] += K3;
+      const R* thp = th + (size_t)s * 3 * P;
+      const R* dthp = dth + (size_t)s * 3 * P;
 #pragma unroll
-    for (int q = 0; q < T; ++q) {
-      const int t1 = ox - q, t2 = oy - q, t3 = oz - q;
-      const bool v1 = t1 >= 0 && t1 < P, v2 = t2 >= 0 && t2 < P, v3 = t3 >= 0 && t3 < P;
-      wx[q] = v1 ? thp[t1] : R(0);
-      dwx[q] = v1 ? dthp[t1] : R(0);
-      wy[q] = v2 ? thp[P + t2] : R(0);
-      dwy[q] = v2 ? dthp[P + t2] : R(0);
-      wz[q] = v3 ? thp[2 * P + t3] : R(0);
-      dwz[q] = v3 ? dthp[2 * P + t3] : R(0);
+      for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+        for (int q = 0; q < T; ++q) {
+          const int t = o[ax] - q;
+          const bool v = t >= 0 && t < P;
+          wts[lane][(2 * ax) * T + q] = v ? thp[ax * P + t] : R(0);
+          wts[lane][(2 * ax + 1) * T + q] = v ? dthp[ax * P + t] : R(0);
+        }
+      sat[lane] = make_int4(s, o[0], o[1], o[2]);
     }
-    const R d0 = dv[(s * 3 + 0) * B + bg];
-    const R d1 = dv[(s * 3 + 1) * B + bg];
-    const R d2 = dv[(s * 3 + 2) * B + bg];
-    if (NSUB == 1) {
-      // uniform point loop: skip rows and points outside the atom's stencil
+    // the batch's LDS writes are visible to the whole wavefront before it reads them
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    int4 at = sat[0];
+    int s = __builtin_amdgcn_readfirstlane(at.x);
+    R n0 = dv[((size_t)s * 3 + 0) * B + bg];
+    R n1 = dv[((size_t)s * 3 + 1) * B + bg];
+    R n2 = dv[((size_t)s * 3 + 2) * B + bg];
+    for (int a = 0; a < na; ++a) {
+      const int ox = __builtin_amdgcn_readfirstlane(at.y);
+      const int oy = __builtin_amdgcn_readfirstlane(at.z);
+      const int oz = __builtin_amdgcn_readfirstlane(at.w);
+      const R d0 = n0, d1 = n1, d2 = n2;
+      if (a + 1 < na) {  // next atom's dipoles while this one is spread
+        at = sat[a + 1];
+        s = __builtin_amdgcn_readfirstlane(at.x);
+        n0 = dv[((size_t)s * 3 + 0) * B + bg];
+        n1 = dv[((size_t)s * 3 + 1) * B + bg];
+        n2 = dv[((size_t)s * 3 + 2) * B + bg];
+      }
+      const R* wa = wts[a];
+      R wx[T], dwx[T], wy[T], dwy[T], wz[T], dwz[T];
 #pragma unroll
-      for (int pz = 0; pz < T; ++pz) {
-        if (oz - pz < 0 || oz - pz >= P) continue;
+      for (int q = 0; q < T; ++q) {
+        wx[q] = wa[q]; dwx[q] = wa[T + q];
+        wy[q] = wa[2 * T + q]; dwy[q] = wa[3 * T + q];
+        wz[q] = wa[4 * T + q]; dwz[q] = wa[5 * T + q];
+      }
+      if (NSUB == 1) {
+        // uniform point loop: skip rows and points outside the atom's stencil
 #pragma unroll
-        for (int py = 0; py < T; ++py) {
-          if (oy - py < 0 || oy - py >= P) continue;
-          const R A = d0 * wy[py] * wz[pz];
-          const R Bc = d1 * dwy[py] * wz[pz] + d2 * wy[py] * dwz[pz];
+        for (int pz = 0; pz < T; ++pz) {
+          if (oz - pz < 0 || oz - pz >= P) continue;
 #pragma unroll
-          for (int px = 0; px < T; ++px) {
-            if (ox - px < 0 || ox - px >= P) continue;
-            acc[(pz * T + py) * T + px] += dwx[px] * A + wx[px] * Bc;
+          for (int py = 0; py < T; ++py) {
+            if (oy - py < 0 || oy - py >= P) continue;
+            const R A = d0 * wy[py] * wz[pz];
+            const R Bc = d1 * dwy[py] * wz[pz] + d2 * wy[py] * dwz[pz];
+#pragma unroll
+            for (int px = 0; px < T; ++px) {
+              if (ox - px < 0 || ox - px >= P) continue;
+              acc[(pz * T + py) * T + px] += dwx[px] * A + wx[px] * Bc;
+            }
           }
         }
-      }
-    } else {
+      } else {
 #pragma unroll
-      for (int i = 0; i < NP; ++i) {
-        const int p = sub + i * NSUB;
-        const int px = p % T, py = (p / T) % T, pz = p / (T * T);
-        acc[i] += (dwx[px] * wy[py] * wz[pz]) * d0 + (wx[px] * dwy[py] * wz[pz]) * d1 +
-                  (wx[px] * wy[py] * dwz[pz]) * d2;
+        for (int i = 0; i < NP; ++i) {
+          const int p = sub + i * NSUB;
+          const int px = p % T, py = (p / T) % T, pz = p / (T * T);
+          acc[i] += (dwx[px] * wy[py] * wz[pz]) * d0 + (wx[px] * dwy[py] * wz[pz]) * d1 +
+                    (wx[px] * wy[py] * dwz[pz]) * d2;
+        }
       }
     }
+    // all reads of this batch are done before the next batch overwrites the stage
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   R* g = grid + (size_t)chunk * chunk_elems;
   const int XS = K1 + 2;
@@ -143,15 +186,17 @@ k_gather_epilogue(const Geometry geo, const int* __restrict__ base, const R* __r
   const int K1 = geo.K[0], K2 = geo.K[1], K3 = geo.K[2];
   const int XS = K1 + 2;
   double dot = 0.0;
-  // Blocks are dealt round-robin to the 8 XCDs; give each XCD one contiguous
-  // (spatially compact) range of sorted atoms so that its L2 holds their stencils.
+  // Blocks are dealt round-robin to the 8 XCDs. Each XCD takes one contiguous range
+  // of sorted atoms and sweeps it with all of its wavefronts side by side (wave lw
+  // takes atoms lo + lw, lo + lw + nwx, ...), so the atoms in flight on an XCD at
+  // any time are consecutive, i.e. spatially compact, and their stencils share L2.
   const int nb8 = gridDim.x / 8;
-  const int lblock = (blockIdx.x % 8) * nb8 + blockIdx.x / 8;
-  const int nw = gridDim.x * 4;
-  const int wid = lblock * 4 + wave;
-  const int s_lo = (int)(((long)geo.n * wid) / nw);
-  const int s_hi = (int)(((long)geo.n * (wid + 1)) / nw);
-  for (int s = s_lo; s < s_hi; ++s) {
+  const int xcd = blockIdx.x % 8;
+  const int nwx = nb8 * 4;
+  const int lw = (blockIdx.x / 8) * 4 + wave;
+  const int x_lo = (int)(((long)geo.n * xcd) / 8);
+  const int x_hi = (int)(((long)geo.n * (xcd + 1)) / 8);
+  for (int s = x_lo + lw; s < x_hi; s += nwx) {
     R e0 = R(0), e1 = R(0), e2 = R(0);
     if (comps & MBD_C_REC) {
       const R* thp = th + s * 3 * P;
@@ -236,7 +281,7 @@ void launch_spread(const Geometry& geo, const SysBuffers& b, int B, int BG, int 
                    int nchunks, hipStream_t st) {
   const size_t chunk = (size_t)geo.K[2] * geo.K[1] * (geo.K[0] + 2) * BG;
   const int ntiles = geo.tiles[0] * geo.tiles[1] * geo.tiles[2];
-  dim3 grd((ntiles + 3) / 4, nchunks);
+  dim3 grd(((ntiles + 3) / 4 + 7) / 8 * 8, nchunks);  // a multiple of 8 (XCD remap)
 #define MBD_SPREAD(PP, BB)                                                                  \
   k_spread<R, PP, BB><<<grd, 256, 0, st>>>(geo, b.tile_start, b.tile_atoms, b.base,        \
                                            (const R*)b.th, (const R*)b.dth, (const R*)b.dv, \
