@@ -32,6 +32,34 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Kernel that implements each timed stage at this workload (float, p = 6, 64-wide chunks).
+STAGE_KERNEL = {
+    "pair": "k_pair_list<float, 1, 2>", "spread": "k_spread<float, 6, 64>",
+    "fft_x": "k_fft_reg<96, 0>", "fft_y": "k_fft_reg<96, 1>", "fft_z_conv": "k_fft_reg<96, 2>",
+    "ifft_y": "k_fft_reg<96, 3>", "ifft_x": "k_fft_reg<96, 4>",
+    "gather": "k_gather_epilogue<float, 6, 64>",
+}
+
+
+def measured_traffic(kernel):
+    """HBM-side bytes per launch (scaled FETCH_SIZE + WRITE_SIZE) recorded in
+    profiles/traffic_water24k.md, or None when absent or when the kernel's source file
+    has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_water24k.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        f = [x.strip() for x in line.split("|")]
+        if len(f) == 7 and f[0] == kernel:
+            src = os.path.join(ROOT, f[1])
+            if not os.path.exists(src):
+                return None
+            sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+            return float(f[5]) + float(f[6]) if sha == f[2] else None
+    return None
+
+
 def stage_bytes(stage, K, N, B):
     """Algorithmic HBM bytes of one launch of a grid stage (B right-hand sides, float32)."""
     K1, K2, K3 = K
@@ -132,7 +160,8 @@ def main():
         achieved = flops / (dom_ms_avg * 1e-3) / 1e12
         roof = {"kernel": "pair", "bound": "alu", "achieved": round(achieved, 3),
                 "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP32_VALU_PEAK_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / FP32_VALU_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic(STAGE_KERNEL.get(dom, "")),
                 "avg_launch_ms": round(dom_ms_avg, 4),
                 "algorithmic_per_launch": f"18 flop x {n_pairs} pairs x {B} rhs"}
     else:
@@ -140,7 +169,7 @@ def main():
         achieved = by / (dom_ms_avg * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "avg_launch_ms": round(dom_ms_avg, 4),
+                "traffic": measured_traffic(STAGE_KERNEL.get(dom, "")), "avg_launch_ms": round(dom_ms_avg, 4),
                 "algorithmic_per_launch": f"{by:.4g} B"}
     # Whole-matvec algorithmic bytes 24 K^3 + 48 N per probe-vector.
     bmv = 24.0 * K[0] * K[1] * K[2] + 48.0 * s.n
