@@ -94,9 +94,10 @@ typedef struct {
   uint64_t seed;        /* probe seed (SplitMix64 counter generator, see below)        */
   int32_t precision;    /* MBD_PREC_FP64 or MBD_PREC_MIXED                              */
   int32_t reorth;       /* MBD_REORTH_NONE / LOCAL / FULL                               */
-  int32_t want_forces;  /* reserved; must be 0 in this version                          */
-  int32_t deterministic;/* reserved; results are run-to-run reproducible up to float
-                           atomics in the spread kernel                                 */
+  int32_t want_forces;  /* 1 => allocate the reverse-sweep workspace so that mbd_execute
+                           can return forces (needs block >= 4); 0 => energy only      */
+  int32_t deterministic;/* reserved: every reduction already runs in a fixed order, so
+                           results are bit-reproducible run to run on one device        */
 } mbd_params;
 
 /* Values derived on the host for one system of a plan. */
@@ -139,7 +140,14 @@ mbd_status mbd_set_positions(mbd_plan plan, int32_t sys, const double* pos);
 
 /* Run Algorithm 1 for every system: R probes in blocks of `block` RHS, m Lanczos steps
  * each, Gauss quadrature per probe, then E = 1/2 (3N/R) sum_l Q_l - 3/2 sum omega.
- * energy: device [n_sys] float64. forces must be NULL in this version. */
+ * energy: device [n_sys] float64.
+ * forces: NULL, or device [sum of N][3] float64 (systems concatenated, caller atom order)
+ *   receiving F = -dE/dR, the exact derivative of the fixed-probe estimator above with
+ *   respect to the positions (forces are future work in the paper's conclusions; this is
+ *   reverse mode through the Lanczos recurrence and the quadrature, with one adjoint
+ *   matvec and the bilinear pair and reciprocal force terms per step). Re-orthogonalization
+ *   corrections are not differentiated (exact for MBD_REORTH_NONE). Requires a plan
+ *   created with want_forces = 1, else MBD_E_STATE. */
 mbd_status mbd_execute(mbd_plan plan, double* energy, double* forces);
 
 /* Synchronize the plan's stream and return the first device-detected error
@@ -180,7 +188,9 @@ enum {
   MBD_STAGE_GATHER = 7,    /* derivative gather + epilogue (l = Omega w + g E*) */
   MBD_STAGE_LANCZOS = 8,   /* recurrence update, reductions, quadrature        */
   MBD_STAGE_SETUP = 9,     /* position-dependent setup                         */
-  MBD_N_STAGES = 10
+  MBD_STAGE_FORCE = 10,    /* pair and reciprocal bilinear force terms         */
+  MBD_STAGE_ADJOINT = 11,  /* tridiagonal adjoint and reverse-sweep vector work */
+  MBD_N_STAGES = 12
 };
 /* enable != 0: from now on every stage launch enqueued by this plan is bracketed by
  * HIP events on the plan's stream (adds a few microseconds per launch). */

@@ -33,6 +33,20 @@ void mbdh_direct_kernel(int32_t prec, double r2, double tau, double inv_s, doubl
 int32_t mbdh_tridiag_quadrature(const double* a, const double* b, int32_t n, double* q,
                                 double* theta_min);
 
+/* As mbdh_bspline, plus ddth[t] = M_p''(w + t) (B-spline second derivatives, used for forces). */
+int32_t mbdh_bspline2(int32_t p, double w, double* th, double* dth, double* ddth);
+
+/* Direct-space kernel and its radial derivatives in double precision: A, B as in
+ * mbdh_direct_kernel and dA_r = A'(r) / r, dB_r = B'(r) / r (pair forces). */
+void mbdh_direct_kernel_grad(double r2, double tau, double inv_s, double damp_d, double* A,
+                             double* B, double* dA_r, double* dB_r);
+
+/* Adjoint of the Gauss quadrature of the tridiagonal (a, b) as above: abar[k] = dQ/da_k and
+ * bbar[k] = dQ/db_{k-1} for k >= 1 (bbar[0] = 0), where b_{k-1} couples rows k-1 and k.
+ * Returns 1 on convergence, else 0. */
+int32_t mbdh_tridiag_adjoint(const double* a, const double* b, int32_t n, double* abar,
+                             double* bbar);
+
 #ifdef __cplusplus
 }
 #endif

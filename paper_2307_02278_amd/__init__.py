@@ -8,4 +8,4 @@ from ._lib import (  # noqa: F401
     C_ALL, C_DIAG, C_DIR, C_REC, C_SELF, PREC_FP64, PREC_MIXED, REORTH_FULL, REORTH_LOCAL,
     REORTH_NONE, MbdError,
 )
-from .api import DeviceSystem, Params, Plan, energy  # noqa: F401
+from .api import DeviceSystem, MBDEnergy, Params, Plan, energy  # noqa: F401

@@ -15,7 +15,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 REORTH_NONE, REORTH_LOCAL, REORTH_FULL = 0, 1, 2
 C_DIAG, C_DIR, C_REC, C_SELF, C_ALL = 1, 2, 4, 8, 15
 STAGES = ["pair", "spread", "fft_x", "fft_y", "fft_z_conv", "ifft_y", "ifft_x", "gather",
-          "lanczos", "setup"]
+          "lanczos", "setup", "force", "adjoint"]
 
 
 class MbdSystem(C.Structure):
@@ -92,6 +92,14 @@ HOSTCHECK_SIGNATURES = [
     ("mbdh_direct_kernel", None, [C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double,
                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("mbdh_tridiag_quadrature", C.c_int32,
+     [C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
+      C.POINTER(C.c_double)]),
+    ("mbdh_bspline2", C.c_int32, [C.c_int32, C.c_double, C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    ("mbdh_direct_kernel_grad", None, [C.c_double, C.c_double, C.c_double, C.c_double,
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    ("mbdh_tridiag_adjoint", C.c_int32,
      [C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
       C.POINTER(C.c_double)]),
 ]

@@ -26,6 +26,7 @@ class Params:
     seed: int = 12345
     precision: int = L.PREC_FP64
     reorth: int = L.REORTH_NONE
+    want_forces: bool = False
 
     def to_c(self) -> L.MbdParams:
         p = L.MbdParams()
@@ -44,7 +45,7 @@ class Params:
         p.seed = self.seed
         p.precision = self.precision
         p.reorth = self.reorth
-        p.want_forces = 0
+        p.want_forces = 1 if self.want_forces else 0
         p.deterministic = 0
         return p
 
@@ -96,10 +97,16 @@ class Plan:
         L.check(self.lib.mbd_plan_info(self.handle, sys, C.byref(inf)))
         return inf
 
-    def execute(self) -> torch.Tensor:
+    def execute(self, forces: bool = False):
+        """E_MBD per system; with forces=True also F = -dE/dR, [sum N, 3] (float64, GPU)."""
         e = torch.zeros(len(self.systems), dtype=torch.float64, device="cuda")
-        L.check(self.lib.mbd_execute(self.handle, C.c_void_p(e.data_ptr()), None))
-        return e
+        if not forces:
+            L.check(self.lib.mbd_execute(self.handle, C.c_void_p(e.data_ptr()), None))
+            return e
+        f = torch.zeros(sum(s.n for s in self.systems), 3, dtype=torch.float64, device="cuda")
+        L.check(self.lib.mbd_execute(self.handle, C.c_void_p(e.data_ptr()),
+                                     C.c_void_p(f.data_ptr())))
+        return e, f
 
     def check(self):
         L.check(self.lib.mbd_check(self.handle))
@@ -167,3 +174,24 @@ def energy(systems: List[DeviceSystem], params: Params) -> torch.Tensor:
         return e
     finally:
         plan.close()
+
+
+class MBDEnergy(torch.autograd.Function):
+    """E_MBD of one system as a differentiable function of its positions.
+
+    forward(pos, plan) sets the positions, runs the plan with forces and returns the
+    energy; backward returns grad_E * dE/dR = -grad_E * F. The plan must have been
+    created with want_forces=True for this system (index 0)."""
+
+    @staticmethod
+    def forward(ctx, pos, plan):
+        plan.set_positions(pos.detach())
+        e, f = plan.execute(forces=True)
+        plan.check()
+        ctx.save_for_backward(f)
+        return e[0]
+
+    @staticmethod
+    def backward(ctx, grad):
+        (f,) = ctx.saved_tensors
+        return -grad * f.to(grad.device), None

@@ -153,13 +153,24 @@ void allocate_system(Plan& plan, System& S, int R_probes, int m) {
   b.dv = dalloc<R>(plan, vec, by);
   b.Ed = dalloc<R>(plan, vec, by);
   b.grid = dalloc<R>(plan, (size_t)g.K[2] * g.K[1] * (g.K[0] + 2) * B, by);
-  b.part = dalloc<double>(plan, (size_t)kRedBlocks * 4 * B, by);
+  b.part = dalloc<double>(plan, (size_t)kRedBlocks * kPartSlots * B, by);
   b.coef = dalloc<double>(plan, (size_t)kMaxSteps * B, by);
   b.a = dalloc<double>(plan, (size_t)R_probes * m, by);
   b.b = dalloc<double>(plan, (size_t)R_probes * m, by);
   b.meff = dalloc<int>(plan, R_probes, by);
   b.q = dalloc<double>(plan, R_probes, by);
   b.sum_omega = dalloc<double>(plan, 1, by);
+  if (plan.forces) {
+    b.ddth = dalloc<R>(plan, 3 * (size_t)n * g.p, by);
+    b.ybar = dalloc<double>(plan, 3 * vec, by);
+    b.lbar = dalloc<double>(plan, vec, by);
+    b.dq = dalloc<R>(plan, vec, by);
+    b.tz = dalloc<double>(plan, (size_t)B * m * m, by);
+    b.abar = dalloc<double>(plan, (size_t)B * m, by);
+    b.bbar = dalloc<double>(plan, (size_t)B * m, by);
+    b.adj = dalloc<double>(plan, (size_t)B * 16, by);
+    b.fsum = dalloc<double>(plan, 3 * (size_t)n, by);
+  }
   std::vector<R> G, tw;
   host_tables<R>(g, G, tw);
   check(hipMemcpy(b.G, G.data(), G.size() * sizeof(R), hipMemcpyHostToDevice), "copy G");
@@ -205,7 +216,61 @@ void create_pair_list(Plan& plan, System& S) {
   b.pg_cap = ((mx + mx / 4 + 32) + 15) / 16 * 16;
   b.pg_hdr = dalloc<int2>(plan, (size_t)ngroups * b.pg_cap, S.bytes);
   b.pg_T = dalloc<R>(plan, (size_t)ngroups * b.pg_cap * kCandStride, S.bytes);
+  if (plan.forces) b.pg_F = dalloc<R>(plan, (size_t)ngroups * b.pg_cap * kCandStride, S.bytes);
   launch_pair_build<R>(S.geo, b, false, plan.stream);
+}
+
+// The adjoint matvec C lbar_k (into Lt) together with the bilinear force terms
+// lbar_k^T dC/dR y_k of one reverse step: the pair part, then per grid chunk the
+// reciprocal part with phi of p = g lbar_k (left by the matvec) and with phi of
+// q = g y_k (one more spread and transform of q).
+template <typename R>
+void adjoint_matvec_forces(Plan& plan, System& S) {
+  const hipStream_t st = plan.stream;
+  const int nch = plan.B / plan.BG;
+  SysBuffers& b = S.buf;
+  SysBuffers bq = b;
+  bq.dv = b.dq;
+  staged(plan, MBD_STAGE_PAIR, [&] { launch_pair<R>(S.geo, b, plan.B, st); });
+  staged(plan, MBD_STAGE_FORCE, [&] { launch_pair_force<R>(S.geo, b, plan.B, st); });
+  for (int c = 0; c < nch; ++c) {
+    staged(plan, MBD_STAGE_SPREAD,
+           [&] { launch_spread<R>(S.geo, b, plan.B, plan.BG, c, 1, st); });
+    for (int pass = 0; pass < 5; ++pass)
+      staged(plan, MBD_STAGE_FFT_X + pass,
+             [&] { launch_fft_pass<R>(S.geo, b, plan.B, plan.BG, c, 1, pass, st); });
+    staged(plan, MBD_STAGE_GATHER, [&] {
+      launch_epilogue<R>(S.geo, b, b.lbar, plan.B, plan.BG, c, 1, MBD_C_ALL, st);
+    });
+    staged(plan, MBD_STAGE_FORCE,
+           [&] { launch_spme_force<R>(S.geo, b, b.dq, plan.B, plan.BG, c, st); });
+    staged(plan, MBD_STAGE_SPREAD,
+           [&] { launch_spread<R>(S.geo, bq, plan.B, plan.BG, c, 1, st); });
+    for (int pass = 0; pass < 5; ++pass)
+      staged(plan, MBD_STAGE_FFT_X + pass,
+             [&] { launch_fft_pass<R>(S.geo, bq, plan.B, plan.BG, c, 1, pass, st); });
+    staged(plan, MBD_STAGE_FORCE,
+           [&] { launch_spme_force<R>(S.geo, b, b.dv, plan.B, plan.BG, c, st); });
+  }
+}
+
+// Reverse sweep for one block of probes (their Krylov vectors are still in W).
+template <typename R>
+void run_backward(Plan& plan, System& S, int l0, int nb) {
+  const hipStream_t st = plan.stream;
+  const int B = plan.B, m = plan.prm.n_steps;
+  const bool fl = sizeof(R) == 4;
+  const size_t vs = 3 * (size_t)S.geo.n * B;
+  staged(plan, MBD_STAGE_ADJOINT, [&] {
+    launch_tridiag_adjoint(S.buf, nb, m, l0, plan.status, st);
+    fill_double(S.buf.ybar, 0.0, 3 * vs, st);
+  });
+  for (int k = m - 1; k >= 0; --k) {
+    staged(plan, MBD_STAGE_ADJOINT,
+           [&] { launch_adjoint_step(S.geo, S.buf, B, nb, k, m, l0, fl, st); });
+    adjoint_matvec_forces<R>(plan, S);
+    staged(plan, MBD_STAGE_ADJOINT, [&] { launch_adjoint_accumulate(S.geo, S.buf, B, k, st); });
+  }
 }
 
 // One application of C to the block stored at w (internal layout), into Lt.
@@ -231,7 +296,10 @@ void matvec_block(Plan& plan, System& S, const double* w, uint32_t comps) {
 }
 
 template <typename R>
-void run_energy(Plan& plan, System& S, int sys_index, double* energy) {
+void run_backward(Plan& plan, System& S, int l0, int nb);
+
+template <typename R>
+void run_energy(Plan& plan, System& S, int sys_index, double* energy, bool forces) {
   const hipStream_t st = plan.stream;
   const int B = plan.B, m = plan.prm.n_steps, R_probes = plan.prm.n_probes;
   const bool fl = sizeof(R) == 4;
@@ -261,6 +329,7 @@ void run_energy(Plan& plan, System& S, int sys_index, double* energy) {
     }
     staged(plan, MBD_STAGE_LANCZOS,
            [&] { launch_tridiag(S.buf, nb, m, l0, plan.status, st); });
+    if (forces) run_backward<R>(plan, S, l0, nb);
   }
   staged(plan, MBD_STAGE_LANCZOS,
          [&] { launch_energy(S.geo, S.buf, R_probes, energy, plan.status, st); });
@@ -348,7 +417,10 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
     return fail(MBD_E_ARG, "precision must be MBD_PREC_FP64 or MBD_PREC_MIXED");
   if (prm.reorth < MBD_REORTH_NONE || prm.reorth > MBD_REORTH_FULL)
     return fail(MBD_E_ARG, "reorth must be NONE, LOCAL or FULL");
-  if (prm.want_forces != 0) return fail(MBD_E_ARG, "forces are not available in this version");
+  if (prm.want_forces != 0 && prm.want_forces != 1)
+    return fail(MBD_E_ARG, "want_forces must be 0 or 1");
+  if (prm.want_forces && prm.block < 4)
+    return fail(MBD_E_ARG, "forces need block >= 4");
   for (int a = 0; a < 3; ++a)
     if (prm.grid[a] < 0) return fail(MBD_E_ARG, "grid sizes must be >= 0");
 
@@ -401,6 +473,7 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
   plan.prec = prm.precision;
   plan.B = prm.block;
   plan.BG = BG_plan;
+  plan.forces = prm.want_forces != 0;
   plan.stream = static_cast<hipStream_t>(stream);
   hipGetDevice(&plan.device);
   try {
@@ -450,11 +523,11 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
       if (plan.prec == MBD_PREC_FP64) {
         allocate_system<double>(plan, S, prm.n_probes, prm.n_steps);
         run_setup<double>(plan, S, sy.pos);
-        if (plan.B >= 16) create_pair_list<double>(plan, S);
+        if (plan.B >= 16 || plan.forces) create_pair_list<double>(plan, S);
       } else {
         allocate_system<float>(plan, S, prm.n_probes, prm.n_steps);
         run_setup<float>(plan, S, sy.pos);
-        if (plan.B >= 16) create_pair_list<float>(plan, S);
+        if (plan.B >= 16 || plan.forces) create_pair_list<float>(plan, S);
       }
       check(hipGetLastError(), "setup launch");
     }
@@ -535,13 +608,22 @@ mbd_status mbd_get_stage_times(mbd_plan plan, double* ms, int64_t* launches) {
 mbd_status mbd_execute(mbd_plan plan, double* energy, double* forces) {
   using namespace mbd;
   if (!plan || !energy) return fail(MBD_E_ARG, "NULL argument");
-  if (forces) return fail(MBD_E_ARG, "forces are not available in this version");
   Plan& P = plan->plan;
+  if (forces && !P.forces)
+    return fail(MBD_E_STATE, "forces requested from a plan created with want_forces = 0");
   try {
     check(hipMemsetAsync(P.status, 0, sizeof(uint32_t), P.stream), "clear status");
+    size_t off = 0;
     for (int s = 0; s < (int)P.sys.size(); ++s) {
-      if (P.prec == MBD_PREC_FP64) run_energy<double>(P, P.sys[s], s, energy + s);
-      else run_energy<float>(P, P.sys[s], s, energy + s);
+      System& S = P.sys[s];
+      if (forces) fill_double(S.buf.fsum, 0.0, 3 * (size_t)S.geo.n, P.stream);
+      if (P.prec == MBD_PREC_FP64) run_energy<double>(P, S, s, energy + s, forces != nullptr);
+      else run_energy<float>(P, S, s, energy + s, forces != nullptr);
+      if (forces)
+        staged(P, MBD_STAGE_ADJOINT, [&] {
+          launch_forces_finish(S.geo, S.buf, P.prm.n_probes, forces + 3 * off, P.stream);
+        });
+      off += (size_t)S.geo.n;
     }
     check(hipGetLastError(), "execute launch");
   } catch (const HipError& e) {

@@ -16,6 +16,7 @@ constexpr int kMaxOrder = 8;
 constexpr int kRedBlocks = 1024;   // blocks (and partial sums) of the row reductions
 constexpr int kSpreadTile = 4;     // grid points per spread-tile edge (one wavefront per tile)
 constexpr int kMaxSteps = 512;
+constexpr int kPartSlots = 8;      // partial-sum slots per reduction block
 // Direct-space tensor list: targets per group, stored components per (source,
 // target) pair (xx, yy, zz, xy, xz, yz) and values per listed source.
 constexpr int kGroup = 16;
@@ -87,6 +88,7 @@ struct SysBuffers {
   int* scell = nullptr;        // [n] Morton cell index of each sorted atom
   void* th = nullptr;          // Real [n][3][p] M_p(w + t)
   void* dth = nullptr;         // Real [n][3][p] (K_a / L_a) M_p'(w + t)
+  void* ddth = nullptr;        // Real [n][3][p] (K_a / L_a)^2 M_p''(w + t) (forces only)
   int* tile_count = nullptr;   // [ntiles + 1]
   int* tile_start = nullptr;   // [ntiles + 1]
   int* tile_atoms = nullptr;   // [n * max tiles per stencil]
@@ -104,13 +106,23 @@ struct SysBuffers {
   void* dv = nullptr;          // Real [n][3][B] generalized dipoles g * w_k
   void* Ed = nullptr;          // Real [n][3][B] direct-space field
   void* grid = nullptr;        // Real [B / BG][K3][K2][K1 + 2][BG]
-  double* part = nullptr;      // [kRedBlocks][4][B] partial sums
+  double* part = nullptr;      // [kRedBlocks][kPartSlots][B] partial sums
   double* coef = nullptr;      // [B][kMaxSteps] reorthogonalization coefficients
   double* a = nullptr;         // [R][m] Lanczos diagonal
   double* b = nullptr;         // [R][m] nrm[l][k] = ||w_k|| (nrm[l][0] = 1)
   int* meff = nullptr;         // [R]
   double* q = nullptr;         // [R] per-probe quadrature
   double* sum_omega = nullptr; // [1]
+  // forces (reverse sweep through the Lanczos recurrence), allocated when requested
+  void* pg_F = nullptr;        // Real [ngroups][pg_cap][kGroup][6] r_x, r_y, r_z, B, A'/r, B'/r
+  double* ybar = nullptr;      // [3][n][3][B] adjoints of y_{k+1}, y_k, y_{k-1} (rotating)
+  double* lbar = nullptr;      // [n][3][B] adjoint of l_k (input of the adjoint matvec)
+  void* dq = nullptr;          // Real [n][3][B] g * y_k
+  double* tz = nullptr;        // [B][m][m] tridiagonal eigenvectors
+  double* abar = nullptr;      // [B][m] dQ/da_k, then the full adjoint of a_k
+  double* bbar = nullptr;      // [B][m] dQ/d nrm_k (k >= 1)
+  double* adj = nullptr;       // [B][8] per-step adjoint scalars
+  double* fsum = nullptr;      // [n][3] sum over probes and steps of l-bar^T dC/dR y (sorted)
 };
 
 struct System {
@@ -133,6 +145,7 @@ struct StageTimer {
 
 struct Plan {
   std::vector<System> sys;
+  bool forces = false;         // buffers for the reverse sweep exist
   mbd_params prm;
   int prec;                    // MBD_PREC_*
   int B;                       // RHS per block
@@ -194,6 +207,22 @@ void launch_pack(const Geometry& g, const SysBuffers& b, const double* v, int nr
                  bool use_float, hipStream_t st);
 void launch_unpack(const Geometry& g, const SysBuffers& b, double* out, int nrhs, int B,
                    hipStream_t st);
+
+// forces
+template <typename R>
+void launch_pair_force(const Geometry& g, const SysBuffers& b, int B, hipStream_t st);
+template <typename R>
+void launch_spme_force(const Geometry& g, const SysBuffers& b, const void* h, int B, int BG,
+                       int chunk0, hipStream_t st);
+void launch_tridiag_adjoint(const SysBuffers& b, int nb, int m, int probe0, uint32_t* status,
+                            hipStream_t st);
+void launch_adjoint_step(const Geometry& g, const SysBuffers& b, int B, int nb, int k, int m,
+                         int probe0, bool use_float, hipStream_t st);
+void launch_adjoint_accumulate(const Geometry& g, const SysBuffers& b, int B, int k,
+                               hipStream_t st);
+void launch_forces_finish(const Geometry& g, const SysBuffers& b, int R, double* forces,
+                          hipStream_t st);
+void fill_double(double* p, double v, size_t n, hipStream_t st);
 
 bool fft_supported(int k);
 void set_error(const std::string& msg);

@@ -39,4 +39,27 @@ int32_t mbdh_tridiag_quadrature(const double* a, const double* b, int32_t n, dou
   return ok;
 }
 
+int32_t mbdh_bspline2(int32_t p, double w, double* th, double* dth, double* ddth) {
+  switch (p) {
+    case 4: mbd::bspline_weights2<4>(w, th, dth, ddth); return 0;
+    case 6: mbd::bspline_weights2<6>(w, th, dth, ddth); return 0;
+    case 8: mbd::bspline_weights2<8>(w, th, dth, ddth); return 0;
+    default: return -1;
+  }
+}
+
+void mbdh_direct_kernel_grad(double r2, double tau, double inv_s, double damp_d, double* A,
+                             double* B, double* dA_r, double* dB_r) {
+  mbd::direct_kernel_grad(r2, tau, inv_s, damp_d, *A, *B, *dA_r, *dB_r);
+}
+
+int32_t mbdh_tridiag_adjoint(const double* a, const double* b, int32_t n, double* abar,
+                             double* bbar) {
+  std::vector<double> d(a, a + n), e(n, 0.0), u((size_t)n * n), work(2 * (size_t)n);
+  for (int k = 0; k + 1 < n; ++k) e[k] = b[k];
+  if (!mbd::tridiag_eigen(d.data(), e.data(), u.data(), n, n)) return 0;
+  mbd::tridiag_sqrt_adjoint(d.data(), u.data(), n, n, work.data(), abar, bbar);
+  return 1;
+}
+
 }  // extern "C"

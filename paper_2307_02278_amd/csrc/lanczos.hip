@@ -103,7 +103,7 @@ k_update(int n, int B, int nb, int k, int m, int probe0, const double* __restric
   red[threadIdx.x] = ss;
   __syncthreads();
   block_reduce_rows(red, RB, ROWS);
-  if (threadIdx.x < RB && b < B) part[((size_t)blockIdx.x * 4 + 1) * B + b] = red[threadIdx.x];
+  if (threadIdx.x < RB && b < B) part[((size_t)blockIdx.x * kPartSlots + 1) * B + b] = red[threadIdx.x];
 }
 
 // Dot products of w with earlier Krylov vectors for re-orthogonalization:
@@ -127,7 +127,7 @@ k_dot(int n, int B, const double* __restrict__ x, const double* __restrict__ y,
   red[threadIdx.x] = ss;
   __syncthreads();
   block_reduce_rows(red, RB, ROWS);
-  if (threadIdx.x < RB && b < B) part[((size_t)blockIdx.x * 4 + slot) * B + b] = red[threadIdx.x];
+  if (threadIdx.x < RB && b < B) part[((size_t)blockIdx.x * kPartSlots + slot) * B + b] = red[threadIdx.x];
 }
 
 // Sum the per-block partials of one slot for each RHS, in a fixed order.
@@ -136,7 +136,7 @@ k_sum_slot(int B, int slot, const double* __restrict__ part, double* __restrict_
   __shared__ double red[256];
   const int b = blockIdx.x;
   double s = 0.0;
-  for (int k = threadIdx.x; k < kRedBlocks; k += 256) s += part[((size_t)k * 4 + slot) * B + b];
+  for (int k = threadIdx.x; k < kRedBlocks; k += 256) s += part[((size_t)k * kPartSlots + slot) * B + b];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
@@ -189,7 +189,7 @@ k_orth_apply(int n, int B, int nb, int m, int probe0, const double* __restrict__
   red[threadIdx.x] = ss;
   __syncthreads();
   block_reduce_rows(red, RB, ROWS);
-  if (threadIdx.x < RB && b < B) part[((size_t)blockIdx.x * 4 + 1) * B + b] = red[threadIdx.x];
+  if (threadIdx.x < RB && b < B) part[((size_t)blockIdx.x * kPartSlots + 1) * B + b] = red[threadIdx.x];
 }
 
 // a_k from the epilogue partials (slot 0).
@@ -307,6 +307,198 @@ __global__ void k_unpack(int n, int nrhs, int B, const int* __restrict__ perm,
   out[((size_t)b * n + perm[s]) * 3 + a] = lt[t];
 }
 
+
+// ---------------------------------------------------------------------------
+// Forces: reverse sweep through the recurrence (derivative of the fixed-probe
+// estimator). In terms of y_k = w_k / nrm_k, l_k = C y_k, b_k = nrm_k:
+//   w_{k+1} = l_k - a_k y_k - b_k y_{k-1},  y_{k+1} = w_{k+1} / b_{k+1},  a_k = y_k . l_k.
+// Going back from k = m-1 with the adjoints abar_k = dQ/da_k, bbar_k = dQ/db_k of the
+// quadrature and ybar (adjoint of y):
+//   wbar  = (ybar_{k+1} - (ybar_{k+1} . y_{k+1}) y_{k+1}) / b_{k+1} + bbar_{k+1} y_{k+1}
+//   abar_k -= wbar . y_k,  bbar_k -= wbar . y_{k-1}
+//   lbar_k = wbar + abar_k y_k
+//   ybar_k += -a_k wbar + abar_k l_k + C lbar_k,  ybar_{k-1} += -b_k wbar
+// and dQ/dR = sum_k lbar_k^T (dC/dR) y_k. l_k is rebuilt from the recurrence
+// (l_k = w_{k+1} + a_k y_k + b_k y_{k-1}); the last one is the stored C w_{m-1}.
+// Re-orthogonalization corrections are not differentiated.
+// ---------------------------------------------------------------------------
+
+// Per probe: eigenvectors of its tridiagonal and the quadrature adjoint.
+__global__ void k_tridiag_adjoint(int nb, int m, int probe0, const double* __restrict__ a,
+                                  const double* __restrict__ nrm, const int* __restrict__ meff,
+                                  double* __restrict__ tz, double* __restrict__ abar,
+                                  double* __restrict__ bbar, uint32_t* __restrict__ status) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const int l = probe0 + b;
+  double d[kMaxSteps], e[kMaxSteps], work[2 * kMaxSteps];
+  const int n = meff[l];
+  for (int k = 0; k < n; ++k) {
+    d[k] = a[l * m + k];
+    e[k] = (k + 1 < n) ? nrm[l * m + k + 1] : 0.0;
+  }
+  double* u = tz + (size_t)b * m * m;
+  double* ab = abar + (size_t)b * m;
+  double* bb = bbar + (size_t)b * m;
+  for (int k = 0; k < m; ++k) ab[k] = bb[k] = 0.0;
+  if (!tridiag_eigen(d, e, u, n, m)) {
+    atomicOr(status, kErrNoConverge);
+    return;
+  }
+  for (int k = 0; k < n; ++k)
+    if (!(d[k] > 0.0)) atomicOr(status, kErrNotPosdef);
+  tridiag_sqrt_adjoint(d, u, n, m, work, ab, bb);
+}
+
+// Five dot products per right-hand side into partial slots 0..4:
+//   ybar_{k+1}.w_{k+1}, ybar_{k+1}.w_k, ybar_{k+1}.w_{k-1}, w_{k+1}.w_k, w_{k+1}.w_{k-1}.
+template <int RB>
+__global__ void __launch_bounds__(256)
+k_adj_dots(int n, int B, const double* __restrict__ yn, const double* __restrict__ wn,
+           const double* __restrict__ wk, const double* __restrict__ wkm1, int has_km1,
+           double* __restrict__ part) {
+  constexpr int ROWS = 256 / RB;
+  __shared__ double red[256];
+  const int lane = threadIdx.x % RB;
+  const int b = blockIdx.y * RB + lane;
+  const int row0 = blockIdx.x * ROWS + threadIdx.x / RB;
+  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (b < B)
+    for (int row = row0; row < 3 * n; row += gridDim.x * ROWS) {
+      const size_t o = (size_t)row * B + b;
+      const double y = yn[o], w1 = wn[o], w0 = wk[o];
+      const double wm = has_km1 ? wkm1[o] : 0.0;
+      s[0] += y * w1;
+      s[1] += y * w0;
+      s[2] += y * wm;
+      s[3] += w1 * w0;
+      s[4] += w1 * wm;
+    }
+  for (int q = 0; q < 5; ++q) {
+    red[threadIdx.x] = s[q];
+    __syncthreads();
+    block_reduce_rows(red, RB, ROWS);
+    if (threadIdx.x < RB && b < B)
+      part[((size_t)blockIdx.x * kPartSlots + q) * B + b] = red[threadIdx.x];
+    __syncthreads();
+  }
+}
+
+// Per-probe scalars of step k from the dot sums (sums[q * B + b]); updates abar_k and
+// bbar_k in place and writes the coefficients of the element-wise update:
+//   c[0] ybar_{k+1} + c[1] w_{k+1} = wbar;  lbar = wbar + c[2] w_k;
+//   l_k = w_{k+1} + c[3] w_k + c[4] w_{k-1} (k < m-1) or c[5] Lt (k = m-1);
+//   ybar_k += c[6] wbar + c[7] l_k;  ybar_{k-1} += c[8] wbar;  q = g c[9] w_k.
+__global__ void k_adj_scalars(int B, int nb, int k, int m, int probe0,
+                              const double* __restrict__ sums, const double* __restrict__ a,
+                              const double* __restrict__ nrm, const int* __restrict__ meff,
+                              double* __restrict__ abar, double* __restrict__ bbar,
+                              double* __restrict__ coef) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  double* c = coef + (size_t)b * 16;
+  for (int q = 0; q < 16; ++q) c[q] = 0.0;
+  if (b >= nb) return;
+  const int l = probe0 + b;
+  const int me = meff[l];
+  if (k >= me) return;
+  const double nk = nrm[l * m + k];
+  const double nkm1 = k > 0 ? nrm[l * m + k - 1] : 1.0;
+  double c0 = 0.0, c1 = 0.0, wy_k = 0.0, wy_km1 = 0.0;
+  if (k + 1 < me) {
+    const double beta = nrm[l * m + k + 1];
+    const double sa = sums[0 * B + b] / beta;
+    const double sb = sums[1 * B + b] / nk;
+    const double sc = k > 0 ? sums[2 * B + b] / nkm1 : 0.0;
+    const double sd = sums[3 * B + b] / (beta * nk);
+    const double se = k > 0 ? sums[4 * B + b] / (beta * nkm1) : 0.0;
+    const double al1 = 1.0 / beta;
+    const double al2 = bbar[(size_t)b * m + k + 1] - sa / beta;
+    c0 = al1;
+    c1 = al2 / beta;
+    wy_k = al1 * sb + al2 * sd;
+    wy_km1 = al1 * sc + al2 * se;
+  }
+  const double ab = abar[(size_t)b * m + k] - wy_k;
+  abar[(size_t)b * m + k] = ab;
+  if (k > 0) bbar[(size_t)b * m + k] -= wy_km1;
+  const double ak = a[l * m + k];
+  c[0] = c0;
+  c[1] = c1;
+  c[2] = ab / nk;
+  c[3] = ak / nk;
+  c[4] = k > 0 ? nk / nkm1 : 0.0;
+  c[5] = 1.0 / nk;
+  c[6] = -ak;
+  c[7] = ab;
+  c[8] = -nk;
+  c[9] = 1.0 / nk;
+}
+
+template <int RB>
+__global__ void __launch_bounds__(256)
+k_adj_update(int n, int B, int k, int m, const double* __restrict__ coef,
+             const double* __restrict__ wn, const double* __restrict__ wk,
+             const double* __restrict__ wkm1, const double* __restrict__ lt,
+             const double* __restrict__ g, double* __restrict__ yn, double* __restrict__ yc,
+             double* __restrict__ yp, double* __restrict__ lbar, double* __restrict__ pd,
+             float* __restrict__ pf, double* __restrict__ qd, float* __restrict__ qf,
+             int use_float) {
+  constexpr int ROWS = 256 / RB;
+  const int lane = threadIdx.x % RB;
+  const int b = blockIdx.y * RB + lane;
+  const int row0 = blockIdx.x * ROWS + threadIdx.x / RB;
+  if (b >= B) return;
+  const double* c = coef + (size_t)b * 16;
+  const double c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3], c4 = c[4], c5 = c[5], c6 = c[6],
+               c7 = c[7], c8 = c[8], c9 = c[9];
+  const bool last = (k + 1 == m);
+  for (int row = row0; row < 3 * n; row += gridDim.x * ROWS) {
+    const size_t o = (size_t)row * B + b;
+    const double w0 = wk[o];
+    double wbar = 0.0, lk;
+    if (!last) {
+      const double w1 = wn[o];
+      wbar = c0 * yn[o] + c1 * w1;
+      lk = w1 + c3 * w0 + (k > 0 ? c4 * wkm1[o] : 0.0);
+    } else {
+      lk = c5 * lt[o];
+    }
+    const double lb = wbar + c2 * w0;
+    yc[o] += c6 * wbar + c7 * lk;
+    if (k > 0) yp[o] += c8 * wbar;
+    lbar[o] = lb;
+    const double gs = g[row / 3];
+    if (use_float) {
+      pf[o] = (float)(gs * lb);
+      qf[o] = (float)(gs * c9 * w0);
+    } else {
+      pd[o] = gs * lb;
+      qd[o] = gs * c9 * w0;
+    }
+  }
+}
+
+__global__ void k_axpy_vec(size_t count, const double* __restrict__ x, double* __restrict__ y) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) y[t] += x[t];
+}
+
+__global__ void k_fill_double(double* __restrict__ p, double v, size_t count) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) p[t] = v;
+}
+
+// F = -dE/dR = -1/2 (3N / R) dsum/dR, back to caller order.
+__global__ void k_forces_finish(int n, int R, const int* __restrict__ perm,
+                                const double* __restrict__ fsum, double* __restrict__ out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const double sc = -0.5 * (3.0 * n / R);
+  const int i = perm[s];
+  for (int a = 0; a < 3; ++a) out[3 * i + a] = sc * fsum[3 * s + a];
+}
+
 inline int rb_for(int B) { return B >= 64 ? 64 : B; }
 
 }  // namespace
@@ -396,6 +588,63 @@ void launch_tridiag(const SysBuffers& b, int nb, int m, int probe0, uint32_t* st
 void launch_energy(const Geometry& geo, const SysBuffers& b, int R, double* energy_out,
                    uint32_t* status, hipStream_t st) {
   k_energy<<<1, 256, 0, st>>>(geo.n, R, b.q, b.g, b.om2, energy_out, status);
+}
+
+
+void fill_double(double* p, double v, size_t n, hipStream_t st) {
+  if (n == 0) return;
+  k_fill_double<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(p, v, n);
+}
+
+void launch_tridiag_adjoint(const SysBuffers& b, int nb, int m, int probe0, uint32_t* status,
+                            hipStream_t st) {
+  k_tridiag_adjoint<<<(nb + 31) / 32, 32, 0, st>>>(nb, m, probe0, b.a, b.b, b.meff, b.tz,
+                                                   b.abar, b.bbar, status);
+}
+
+// One reverse step k: dots, scalars and the element-wise update, which leaves lbar_k in
+// b.lbar, g * lbar_k in b.dv and g * y_k in b.dq for the adjoint matvec and force terms.
+void launch_adjoint_step(const Geometry& geo, const SysBuffers& b, int B, int nb, int k, int m,
+                         int probe0, bool use_float, hipStream_t st) {
+  const size_t vs = (size_t)geo.n * 3 * B;
+  const int rb = rb_for(B);
+  dim3 grd(kRedBlocks, (B + rb - 1) / rb);
+  double* Y0 = b.ybar;
+  double* yn = Y0 + (size_t)((k + 1) % 3) * vs;
+  double* yc = Y0 + (size_t)(k % 3) * vs;
+  double* yp = Y0 + (size_t)((k + 2) % 3) * vs;
+  // ybar_{k-1} starts from zero (its buffer last held ybar_{k+2})
+  fill_double(yp, 0.0, vs, st);
+  const double* wk = b.W + (size_t)k * vs;
+  const double* wn = (k + 1 < m) ? b.W + (size_t)(k + 1) * vs : wk;
+  const double* wkm1 = k > 0 ? b.W + (size_t)(k - 1) * vs : wk;
+  if (k + 1 < m) {
+    MBD_RB_SWITCH(rb, (k_adj_dots<RB><<<grd, 256, 0, st>>>(geo.n, B, yn, wn, wk, wkm1,
+                                                           k > 0 ? 1 : 0, b.part)));
+    for (int q = 0; q < 5; ++q)
+      k_sum_slot<<<B, 256, 0, st>>>(B, q, b.part, b.coef + (size_t)q * B);
+  } else {
+    fill_double(b.coef, 0.0, (size_t)5 * B, st);
+  }
+  k_adj_scalars<<<(B + 63) / 64, 64, 0, st>>>(B, nb, k, m, probe0, b.coef, b.a, b.b, b.meff,
+                                              b.abar, b.bbar, b.adj);
+  MBD_RB_SWITCH(rb, (k_adj_update<RB><<<grd, 256, 0, st>>>(
+                         geo.n, B, k, m, b.adj, wn, wk, wkm1, b.Lt, b.g, yn, yc, yp, b.lbar,
+                         (double*)b.dv, (float*)b.dv, (double*)b.dq, (float*)b.dq,
+                         use_float ? 1 : 0)));
+}
+
+// ybar_k += C lbar_k (the adjoint matvec's output in b.Lt).
+void launch_adjoint_accumulate(const Geometry& geo, const SysBuffers& b, int B, int k,
+                               hipStream_t st) {
+  const size_t vs = (size_t)geo.n * 3 * B;
+  k_axpy_vec<<<(unsigned)((vs + 255) / 256), 256, 0, st>>>(vs, b.Lt,
+                                                          b.ybar + (size_t)(k % 3) * vs);
+}
+
+void launch_forces_finish(const Geometry& geo, const SysBuffers& b, int R, double* forces,
+                          hipStream_t st) {
+  k_forces_finish<<<(geo.n + 255) / 256, 256, 0, st>>>(geo.n, R, b.perm, b.fsum, forces);
 }
 
 void launch_pack(const Geometry& geo, const SysBuffers& b, const double* v, int nrhs, int B,

@@ -57,6 +57,38 @@ MBD_HD void bspline_weights(double w, double* th, double* dth) {
   for (int t = 0; t < P; ++t) th[t] = M[t];
 }
 
+// Same, plus the second derivatives ddth[t] = M_p''(w + t) = M_{p-2}(w + t)
+// - 2 M_{p-2}(w + t - 1) + M_{p-2}(w + t - 2) (needed for forces; p >= 4).
+template <int P>
+MBD_HD void bspline_weights2(double w, double* th, double* dth, double* ddth) {
+  double M[P];
+#pragma unroll
+  for (int t = 0; t < P; ++t) M[t] = 0.0;
+  M[0] = w;
+  M[1] = 1.0 - w;
+#pragma unroll
+  for (int n = 3; n <= P; ++n) {
+    if (n == P - 1) {
+#pragma unroll
+      for (int t = 0; t < P; ++t)
+        ddth[t] = M[t] - 2.0 * (t > 0 ? M[t - 1] : 0.0) + (t > 1 ? M[t - 2] : 0.0);
+    }
+    if (n == P) {
+#pragma unroll
+      for (int t = 0; t < P; ++t) dth[t] = M[t] - (t > 0 ? M[t - 1] : 0.0);
+    }
+    const double inv = 1.0 / (n - 1);
+#pragma unroll
+    for (int t = n - 1; t >= 0; --t) {
+      const double x = w + t;
+      const double lo = (t > 0) ? M[t - 1] : 0.0;
+      M[t] = (x * M[t] + (n - x) * lo) * inv;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < P; ++t) th[t] = M[t];
+}
+
 // ---------------------------------------------------------------------------
 // Direct-space Ewald dipole kernel with the damping correction (eq. fld_ewald):
 //   T_dir(r) = T_erfc(r) - (1 - f(r)) T(r) = A(r) I - B(r) r r^T,
@@ -131,6 +163,38 @@ MBD_HD void direct_kernel(R r2, R tau, R inv_s, R damp_d, R& A, R& B) {
 // Returns sum_k q_k^2 sqrt(theta_k); *theta_min gets min theta; *ok = 0 when
 // the iteration did not converge.
 // ---------------------------------------------------------------------------
+// Radial derivatives of the direct-space kernel for forces, in double precision:
+// with T_dir = A I - B r r^T, returns A, B, A'(r)/r and B'(r)/r. For the screened part
+// (a -grad grad of a radial function) A_e' = -r B_e; with x = tau r,
+// c = (2x/sqrt(pi)) e^{-x^2}, N = 3 erfc(x) + c (3 + 2x^2): B_e = N / r^5 and
+// B_e' = -(4 x^4 c + 5 N) / r^6. The damping term (1 - f) T has f' = f (1 - f) d / S.
+MBD_HD void direct_kernel_grad(double r2, double tau, double inv_s, double damp_d, double& A,
+                               double& B, double& dA_r, double& dB_r) {
+  direct_kernel<double>(r2, tau, inv_s, damp_d, A, B);
+  const double r = sqrt(r2);
+  const double ir = 1.0 / r, ir2 = ir * ir;
+  const double ir5 = ir2 * ir2 * ir, ir7 = ir5 * ir2;
+  const double x = tau * r, x2 = x * x;
+  const double c = 1.1283791670955126 * x * exp(-x2);
+  const double N = 3.0 * erfc(x) + c * (3.0 + 2.0 * x2);
+  const double Be = N * ir5;
+  const double dBe_r = -(4.0 * x2 * x2 * c + 5.0 * N) * ir7;
+  const double z = damp_d * (r * inv_s - 1.0);
+  double f, omf;
+  if (z >= 0.0) {
+    const double e = exp(-z);
+    omf = e / (1.0 + e);
+    f = 1.0 / (1.0 + e);
+  } else {
+    const double e = exp(z);
+    f = e / (1.0 + e);
+    omf = 1.0 / (1.0 + e);
+  }
+  const double fp = f * omf * damp_d * inv_s;  // df/dr
+  dA_r = -Be + fp * ir2 * ir2 + 3.0 * omf * ir5;
+  dB_r = dBe_r + 3.0 * fp * ir5 * ir + 15.0 * omf * ir7;
+}
+
 MBD_HD double tridiag_sqrt_quadrature(double* d, double* e, double* q, int n,
                                       double* theta_min, int* ok) {
   for (int k = 0; k < n; ++k) q[k] = (k == 0) ? 1.0 : 0.0;
@@ -181,6 +245,85 @@ MBD_HD double tridiag_sqrt_quadrature(double* d, double* e, double* q, int n,
   }
   *theta_min = tmin;
   return sum;
+}
+
+// Same iteration, tracking the full eigenvector matrix U (row-major, u[i * ld + k] =
+// U_ik, columns are eigenvectors) instead of its first row. On return d holds the
+// eigenvalues. Returns 0 if the iteration did not converge.
+MBD_HD int tridiag_eigen(double* d, double* e, double* u, int n, int ld) {
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) u[i * ld + k] = (i == k) ? 1.0 : 0.0;
+  int hi = n - 1;
+  int iter = 0;
+  const double eps = 2.220446049250313e-16;
+  while (hi > 0) {
+    if (fabs(e[hi - 1]) <= eps * (fabs(d[hi - 1]) + fabs(d[hi]))) {
+      e[hi - 1] = 0.0;
+      --hi;
+      continue;
+    }
+    int lo = hi - 1;
+    while (lo > 0 && fabs(e[lo - 1]) > eps * (fabs(d[lo - 1]) + fabs(d[lo]))) --lo;
+    if (++iter > 60 * n) return 0;
+    const double delta = 0.5 * (d[hi - 1] - d[hi]);
+    const double eh = e[hi - 1];
+    const double den = delta + (delta >= 0.0 ? 1.0 : -1.0) * sqrt(delta * delta + eh * eh);
+    const double mu = (den != 0.0) ? d[hi] - eh * eh / den : d[hi];
+    double x = d[lo] - mu;
+    double z = e[lo];
+    for (int k = lo; k < hi; ++k) {
+      const double r = hypot(x, z);
+      double c = 1.0, s = 0.0;
+      if (r != 0.0) { c = x / r; s = -z / r; }
+      if (k > lo) e[k - 1] = r;
+      const double dk = d[k], dk1 = d[k + 1], ek = e[k];
+      d[k] = c * c * dk - 2.0 * c * s * ek + s * s * dk1;
+      d[k + 1] = s * s * dk + 2.0 * c * s * ek + c * c * dk1;
+      e[k] = c * s * (dk - dk1) + (c * c - s * s) * ek;
+      if (k + 1 < hi) {
+        z = -s * e[k + 1];
+        e[k + 1] = c * e[k + 1];
+        x = e[k];
+      }
+      for (int i = 0; i < n; ++i) {
+        const double a0 = u[i * ld + k], a1 = u[i * ld + k + 1];
+        u[i * ld + k] = c * a0 - s * a1;
+        u[i * ld + k + 1] = s * a0 + c * a1;
+      }
+    }
+  }
+  return 1;
+}
+
+// Adjoint of the Gauss quadrature Q = e1^T sqrt(T) e1 with respect to the
+// tridiagonal T = U diag(theta) U^T: dQ/dT = U (F o c c^T) U^T with c = U^T e1 and the
+// divided differences F_ij = 1 / (sqrt(theta_i) + sqrt(theta_j)) of the square root
+// (Daleckii-Krein). Returns abar[k] = dQ/dT_kk and bbar[k] = dQ/dT_{k-1,k} +
+// dQ/dT_{k,k-1} for k >= 1 (bbar[0] = 0). u (ld >= n) and theta come from
+// tridiag_eigen; work needs 2 n doubles.
+MBD_HD void tridiag_sqrt_adjoint(const double* theta, const double* u, int n, int ld,
+                                 double* work, double* abar, double* bbar) {
+  double* sq = work;
+  double* v = work + n;
+  for (int i = 0; i < n; ++i) sq[i] = sqrt(theta[i] > 0.0 ? theta[i] : 0.0);
+  for (int k = 0; k < n; ++k) {
+    // v = (F o c c^T) U[k, :]^T, with c = U[0, :]
+    for (int i = 0; i < n; ++i) {
+      double acc = 0.0;
+      for (int j = 0; j < n; ++j) {
+        const double den = sq[i] + sq[j];
+        acc += (den > 0.0 ? 1.0 / den : 0.0) * u[j] * u[k * ld + j];
+      }
+      v[i] = acc * u[i];
+    }
+    double mkk = 0.0, mkm = 0.0;
+    for (int i = 0; i < n; ++i) {
+      mkk += u[k * ld + i] * v[i];
+      if (k > 0) mkm += u[(k - 1) * ld + i] * v[i];
+    }
+    abar[k] = mkk;
+    bbar[k] = (k > 0) ? 2.0 * mkm : 0.0;
+  }
 }
 
 }  // namespace mbd

@@ -106,8 +106,8 @@ template <typename R>
 __global__ void __launch_bounds__(256)
 k_pair_build(const Geometry geo, const int* __restrict__ cell_start,
              const int* __restrict__ scell, const R* __restrict__ loc, int cap,
-             int2* __restrict__ hdr, R* __restrict__ Tg, int* __restrict__ gcount,
-             int* __restrict__ maxcount) {
+             int2* __restrict__ hdr, R* __restrict__ Tg, R* __restrict__ Fg,
+             int* __restrict__ gcount, int* __restrict__ maxcount) {
   __shared__ R tgt_all[4][kGroup][4];
   __shared__ int tcell_all[4][kGroup][3];
   const int wave = threadIdx.x >> 6;
@@ -208,6 +208,18 @@ k_pair_build(const Geometry geo, const int* __restrict__ cell_start,
               o[3] = -Bk * rx * ry;
               o[4] = -Bk * rx * rz;
               o[5] = -Bk * ry * rz;
+              if (Fg) {
+                // radial data for forces, evaluated in double precision
+                double Ad = 0.0, Bd = 0.0, dA = 0.0, dB = 0.0;
+                if ((mask >> t) & 1u) {
+                  const double r2 = (double)rx * rx + (double)ry * ry + (double)rz * rz;
+                  direct_kernel_grad(r2, geo.tau, 1.0 / ((double)ps + (double)tgt[t][3]),
+                                     geo.damp_d, Ad, Bd, dA, dB);
+                }
+                R* f = Fg + e * kCandStride + t * kTensorWords;
+                f[0] = rx; f[1] = ry; f[2] = rz;
+                f[3] = (R)Bd; f[4] = (R)dA; f[5] = (R)dB;
+              }
             }
           }
           count += nk;
@@ -294,6 +306,120 @@ k_pair_list(const Geometry geo, const int2* __restrict__ hdr, const R* __restric
       Ed[((size_t)i * 3 + 0) * B + rhs] = acc[k][0];
       Ed[((size_t)i * 3 + 1) * B + rhs] = acc[k][1];
       Ed[((size_t)i * 3 + 2) * B + rhs] = acc[k][2];
+    }
+  }
+}
+
+
+// Direct-space part of the bilinear force term for one reverse step: with
+// p = g * lbar_k and q = g * y_k, dS/dR_t for S = sum_(t,j,n) p_t^T T_dir(r) q_j is
+//   dS/dR_t = -sum_(j,n) grad_r u,  u = p_t^T T_dir(r) q_j + q_t^T T_dir(r) p_j,
+// r = R_j + n - R_t; with T_dir = A I - B r r^T, X = p_t.q_j + q_t.p_j and
+// Y = (p_t.r)(q_j.r) + (q_t.r)(p_j.r):
+//   grad_r u = r (A'/r X - B'/r Y) - B [p_t (q_j.r) + q_j (p_t.r) + q_t (p_j.r) + p_j (q_t.r)].
+// Same group and lane layout as k_pair_list; TP target slots per pass keep p_t and q_t
+// in registers. The sum over right-hand sides is reduced per target and added to
+// fsum (each group owns its targets: no atomics, fixed order).
+template <typename R, int NSUB, int WPB, int TP>
+__global__ void __launch_bounds__(64 * WPB)
+k_pair_force(const Geometry geo, const int2* __restrict__ hdr, const R* __restrict__ Fg,
+             const int* __restrict__ gcount, int cap, const R* __restrict__ pv,
+             const R* __restrict__ qv, double* __restrict__ fsum, int B) {
+  constexpr int NT = 64 * WPB;
+  constexpr int CH = 16 * WPB;
+  constexpr int KT = kGroup / NSUB;
+  constexpr int NPASS = KT / TP;
+  constexpr int BW = 64 / NSUB;
+  constexpr int W16 = (int)(kCandStride * sizeof(R) / 16);
+  __shared__ uint4 Fl4[CH * W16];
+  __shared__ int2 hl[CH];
+  __shared__ double red[WPB][kGroup][3];
+  const R* Fl = reinterpret_cast<const R*>(Fl4);
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int rhs = wave * 64 + lane % BW;
+  const int sub = lane / BW;
+  const int per = (gridDim.x + 7) / 8;
+  const int group = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int ngroups = (geo.n + kGroup - 1) / kGroup;
+  if (group >= ngroups) return;  // uniform over the work-group
+  const int cnt = min(gcount[group], cap);
+  const int2* H = hdr + (size_t)group * cap;
+  const uint4* F4 = reinterpret_cast<const uint4*>(Fg + (size_t)group * cap * kCandStride);
+  for (int pass = 0; pass < NPASS; ++pass) {
+    R pt[TP][3], qt[TP][3], G[TP][3];
+#pragma unroll
+    for (int k = 0; k < TP; ++k) {
+      const int i = group * kGroup + (pass * TP + k) * NSUB + sub;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        pt[k][a] = i < geo.n ? pv[((size_t)i * 3 + a) * B + rhs] : R(0);
+        qt[k][a] = i < geo.n ? qv[((size_t)i * 3 + a) * B + rhs] : R(0);
+        G[k][a] = R(0);
+      }
+    }
+    for (int c0 = 0; c0 < cnt; c0 += CH) {
+      const int nc = min(CH, cnt - c0);
+      __syncthreads();
+      for (int w = tid; w < nc * W16; w += NT) Fl4[w] = F4[(size_t)c0 * W16 + w];
+      if (tid < nc) hl[tid] = H[c0 + tid];
+      __syncthreads();
+      for (int c = 0; c < nc; ++c) {
+        const int2 h = hl[c];
+        const int j = __builtin_amdgcn_readfirstlane(h.x);
+        const uint32_t msk = (uint32_t)__builtin_amdgcn_readfirstlane(h.y);
+        const R* pj = pv + (size_t)j * 3 * B + rhs;
+        const R* qj = qv + (size_t)j * 3 * B + rhs;
+        const R p0 = pj[0], p1 = pj[B], p2 = pj[2 * B];
+        const R q0 = qj[0], q1 = qj[B], q2 = qj[2 * B];
+        const R* Fc = Fl + c * kCandStride + sub * kTensorWords;
+#pragma unroll
+        for (int k = 0; k < TP; ++k) {
+          const int slot = pass * TP + k;
+          if ((msk >> (slot * NSUB)) & ((1u << NSUB) - 1u)) {
+            const R* f = Fc + slot * NSUB * kTensorWords;
+            const R rx = f[0], ry = f[1], rz = f[2], Bk = f[3], c1 = f[4], c2 = f[5];
+            const R prt = pt[k][0] * rx + pt[k][1] * ry + pt[k][2] * rz;
+            const R qrt = qt[k][0] * rx + qt[k][1] * ry + qt[k][2] * rz;
+            const R prj = p0 * rx + p1 * ry + p2 * rz;
+            const R qrj = q0 * rx + q1 * ry + q2 * rz;
+            const R X = pt[k][0] * q0 + pt[k][1] * q1 + pt[k][2] * q2 + qt[k][0] * p0 +
+                        qt[k][1] * p1 + qt[k][2] * p2;
+            const R Y = prt * qrj + qrt * prj;
+            const R sc = c1 * X - c2 * Y;
+            G[k][0] -= sc * rx - Bk * (pt[k][0] * qrj + q0 * prt + qt[k][0] * prj + p0 * qrt);
+            G[k][1] -= sc * ry - Bk * (pt[k][1] * qrj + q1 * prt + qt[k][1] * prj + p1 * qrt);
+            G[k][2] -= sc * rz - Bk * (pt[k][2] * qrj + q2 * prt + qt[k][2] * prj + p2 * qrt);
+          }
+        }
+      }
+    }
+    // sum over the right-hand sides: the BW lanes of a target subset, then the waves
+#pragma unroll
+    for (int k = 0; k < TP; ++k) {
+      double g0 = G[k][0], g1 = G[k][1], g2 = G[k][2];
+      for (int off = 1; off < BW; off <<= 1) {
+        g0 += __shfl_xor(g0, off);
+        g1 += __shfl_xor(g1, off);
+        g2 += __shfl_xor(g2, off);
+      }
+      const int t = (pass * TP + k) * NSUB + sub;
+      if (lane % BW == 0) {
+        red[wave][t][0] = g0;
+        red[wave][t][1] = g1;
+        red[wave][t][2] = g2;
+      }
+    }
+    __syncthreads();
+    if (tid < kGroup * 3) {
+      const int t = tid / 3, a = tid % 3;
+      if ((t / NSUB) / TP == pass) {  // target t was handled in this pass
+        double v = 0.0;
+        for (int w = 0; w < WPB; ++w) v += red[w][t][a];
+        const int i = group * kGroup + t;
+        if (i < geo.n) fsum[3 * (size_t)i + a] += v;
+      }
     }
   }
 }
@@ -385,8 +511,34 @@ void launch_pair_build(const Geometry& g, const SysBuffers& b, bool count_only, 
   fill_int(b.pg_max, 0, 1, st);
   k_pair_build<R><<<(ngroups + 3) / 4, 256, 0, st>>>(
       g, b.cell_start, b.scell, (const R*)b.loc, count_only ? 0 : b.pg_cap, b.pg_hdr,
-      (R*)b.pg_T, b.pg_count, b.pg_max);
+      (R*)b.pg_T, count_only ? nullptr : (R*)b.pg_F, b.pg_count, b.pg_max);
 }
+
+template <typename R>
+void launch_pair_force(const Geometry& g, const SysBuffers& b, int B, hipStream_t st) {
+  const int ngroups = (g.n + kGroup - 1) / kGroup;
+  const int nblk = (ngroups + 7) / 8 * 8;
+  const int2* H = b.pg_hdr;
+  const R* F = (const R*)b.pg_F;
+  const R* p = (const R*)b.dv;
+  const R* q = (const R*)b.dq;
+#define MBD_PF(NS, WP, TPV, TH)                                                    \
+  k_pair_force<R, NS, WP, TPV><<<nblk, TH, 0, st>>>(g, H, F, b.pg_count, b.pg_cap, p, q, \
+                                                    b.fsum, B)
+  switch (B) {
+    case 4: MBD_PF(16, 1, 1, 64); break;
+    case 8: MBD_PF(8, 1, 2, 64); break;
+    case 16: MBD_PF(4, 1, 4, 64); break;
+    case 32: MBD_PF(2, 1, 8, 64); break;
+    case 64: MBD_PF(1, 1, 8, 64); break;
+    case 128: MBD_PF(1, 2, 8, 128); break;
+    default: MBD_PF(1, 4, 8, 256); break;
+  }
+#undef MBD_PF
+}
+
+template void launch_pair_force<float>(const Geometry&, const SysBuffers&, int, hipStream_t);
+template void launch_pair_force<double>(const Geometry&, const SysBuffers&, int, hipStream_t);
 
 template void launch_pair<float>(const Geometry&, const SysBuffers&, int, hipStream_t);
 template void launch_pair<double>(const Geometry&, const SysBuffers&, int, hipStream_t);

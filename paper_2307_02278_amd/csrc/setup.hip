@@ -100,7 +100,8 @@ __global__ void k_sorted_tables(Geometry geo, const int* __restrict__ perm,
                                 const double* __restrict__ rvdw, R* __restrict__ loc,
                                 double* __restrict__ g, double* __restrict__ om2,
                                 int* __restrict__ base, R* __restrict__ th, R* __restrict__ dth,
-                                int* __restrict__ tile_count, int* __restrict__ scell) {
+                                R* __restrict__ ddth, int* __restrict__ tile_count,
+                                int* __restrict__ scell) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= geo.n) return;
   const int i = perm[s];
@@ -125,9 +126,14 @@ __global__ void k_sorted_tables(Geometry geo, const int* __restrict__ perm,
     b0 %= geo.K[a];
     if (b0 < 0) b0 += geo.K[a];
     base[3 * s + a] = b0;
-    double t[P], dt[P];
-    bspline_weights<P>(w, t, dt);
+    double t[P], dt[P], ddt[P];
     const double scale = geo.K[a] / geo.L[a];
+    if (ddth) {
+      bspline_weights2<P>(w, t, dt, ddt);
+      for (int k = 0; k < P; ++k) ddth[(s * 3 + a) * P + k] = (R)(ddt[k] * scale * scale);
+    } else {
+      bspline_weights<P>(w, t, dt);
+    }
     for (int k = 0; k < P; ++k) {
       th[(s * 3 + a) * P + k] = (R)t[k];
       dth[(s * 3 + a) * P + k] = (R)(dt[k] * scale);
@@ -229,7 +235,7 @@ void launch_setup(const Geometry& g, SysBuffers& b, const double* pos, const dou
 #define MBD_TABLES(PP)                                                                        \
   k_sorted_tables<R, PP><<<blocks_for(g.n, 128), 128, 0, st>>>(                               \
       g, b.perm, b.wpos, alpha, omega, rvdw, (R*)b.loc, b.g, b.om2, b.base, (R*)b.th,        \
-      (R*)b.dth, b.tile_count, b.scell)
+      (R*)b.dth, (R*)b.ddth, b.tile_count, b.scell)
   switch (g.p) {
     case 4: MBD_TABLES(4); break;
     case 6: MBD_TABLES(6); break;

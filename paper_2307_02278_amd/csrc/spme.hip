@@ -270,7 +270,100 @@ k_gather_epilogue(const Geometry geo, const int* __restrict__ base, const R* __r
     double t = 0.0;
     for (int wv = 0; wv < 4; ++wv)
       for (int sb = 0; sb < NSUB; ++sb) t += red[wv * 64 + sb * BG + threadIdx.x];
-    part[((size_t)blockIdx.x * 4 + 0) * B + chunk * BG + threadIdx.x] = t;
+    part[((size_t)blockIdx.x * kPartSlots + 0) * B + chunk * BG + threadIdx.x] = t;
+  }
+}
+
+// Reciprocal-space part of the bilinear force term for one reverse step: with
+// S = D_p^T phi_q (D_x the spread of dipoles x, phi_x = G~ * D_x, symmetric in p, q),
+//   dS/dR_a = sum_k H_a(k) (p_a phi_q(k) + q_a phi_p(k)),  H_a(k) = grad_a grad_a W_a(k),
+// the Hessian of the atom's weight product (d^2/du^2 along one axis: ddth; mixed
+// axes: dth dth). One call adds sum_k H_a(k) h_a phi(k) for one grid (phi) and the
+// other dipole set h, summed over the chunk's right-hand sides, to fsum (wavefront
+// per atom, lanes over right-hand sides and stencil rows as in the gather).
+template <typename R, int P, int BG>
+__global__ void __launch_bounds__(256)
+k_spme_force(const Geometry geo, const int* __restrict__ base, const R* __restrict__ th,
+             const R* __restrict__ dth, const R* __restrict__ ddth, const R* __restrict__ grid,
+             size_t chunk_elems, const R* __restrict__ hv, int B, int chunk0,
+             double* __restrict__ fsum) {
+  constexpr int NSUB = Lanes<BG>::NSUB;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int b = lane % BG;
+  const int sub = lane / BG;
+  const int chunk = blockIdx.y + chunk0;
+  const int bg = chunk * BG + b;
+  const R* gr = grid + (size_t)chunk * chunk_elems;
+  const int K1 = geo.K[0], K2 = geo.K[1], K3 = geo.K[2];
+  const int XS = K1 + 2;
+  const int nb8 = gridDim.x / 8;
+  const int xcd = blockIdx.x % 8;
+  const int nwx = nb8 * 4;
+  const int lw = (blockIdx.x / 8) * 4 + wave;
+  const int x_lo = (int)(((long)geo.n * xcd) / 8);
+  const int x_hi = (int)(((long)geo.n * (xcd + 1)) / 8);
+  for (int s = x_lo + lw; s < x_hi; s += nwx) {
+    const R* tp = th + (size_t)s * 3 * P;
+    const R* dp = dth + (size_t)s * 3 * P;
+    const R* ddp = ddth + (size_t)s * 3 * P;
+    R mx[P], dmx[P], ddmx[P], my[P], dmy[P], ddmy[P], mz[P], dmz[P], ddmz[P];
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+      mx[t] = tp[t]; dmx[t] = dp[t]; ddmx[t] = ddp[t];
+      my[t] = tp[P + t]; dmy[t] = dp[P + t]; ddmy[t] = ddp[P + t];
+      mz[t] = tp[2 * P + t]; dmz[t] = dp[2 * P + t]; ddmz[t] = ddp[2 * P + t];
+    }
+    const int bx = base[3 * s], by = base[3 * s + 1], bz = base[3 * s + 2];
+    int kxs[P];
+#pragma unroll
+    for (int t1 = 0; t1 < P; ++t1) {
+      int k1 = bx - t1;
+      if (k1 < 0) k1 += K1;
+      kxs[t1] = k1 * BG + b;
+    }
+    R hxx = R(0), hyy = R(0), hzz = R(0), hxy = R(0), hxz = R(0), hyz = R(0);
+#pragma unroll
+    for (int t3 = 0; t3 < P; ++t3) {
+      int k3 = bz - t3;
+      if (k3 < 0) k3 += K3;
+#pragma unroll
+      for (int t2 = 0; t2 < P; ++t2) {
+        if ((t3 * P + t2) % NSUB != sub) continue;
+        int k2 = by - t2;
+        if (k2 < 0) k2 += K2;
+        const R* line = gr + ((size_t)k3 * K2 + k2) * XS * BG;
+        R s0 = R(0), s1 = R(0), s2 = R(0);
+#pragma unroll
+        for (int t1 = 0; t1 < P; ++t1) {
+          const R phi = line[kxs[t1]];
+          s0 += mx[t1] * phi;
+          s1 += dmx[t1] * phi;
+          s2 += ddmx[t1] * phi;
+        }
+        hxx += s2 * my[t2] * mz[t3];
+        hyy += s0 * ddmy[t2] * mz[t3];
+        hzz += s0 * my[t2] * ddmz[t3];
+        hxy += s1 * dmy[t2] * mz[t3];
+        hxz += s1 * my[t2] * dmz[t3];
+        hyz += s0 * dmy[t2] * dmz[t3];
+      }
+    }
+    const size_t o = (size_t)s * 3 * B + bg;
+    const R h0 = hv[o], h1 = hv[o + B], h2 = hv[o + 2 * B];
+    double f0 = (double)(hxx * h0 + hxy * h1 + hxz * h2);
+    double f1 = (double)(hxy * h0 + hyy * h1 + hyz * h2);
+    double f2 = (double)(hxz * h0 + hyz * h1 + hzz * h2);
+    for (int off = 1; off < 64; off <<= 1) {
+      f0 += __shfl_xor(f0, off);
+      f1 += __shfl_xor(f1, off);
+      f2 += __shfl_xor(f2, off);
+    }
+    if (lane == 0) {
+      fsum[3 * (size_t)s] += f0;
+      fsum[3 * (size_t)s + 1] += f1;
+      fsum[3 * (size_t)s + 2] += f2;
+    }
   }
 }
 
@@ -333,6 +426,39 @@ void launch_epilogue(const Geometry& geo, const SysBuffers& b, const double* w, 
 #undef MBD_GATHER_P
 #undef MBD_GATHER
 }
+
+template <typename R>
+void launch_spme_force(const Geometry& geo, const SysBuffers& b, const void* h, int B, int BG,
+                       int chunk0, hipStream_t st) {
+  const size_t chunk = (size_t)geo.K[2] * geo.K[1] * (geo.K[0] + 2) * BG;
+  dim3 grd(kRedBlocks, 1);
+#define MBD_SF(PP, BB)                                                                      \
+  k_spme_force<R, PP, BB><<<grd, 256, 0, st>>>(geo, b.base, (const R*)b.th, (const R*)b.dth, \
+                                               (const R*)b.ddth, (const R*)b.grid, chunk,     \
+                                               (const R*)h, B, chunk0, b.fsum)
+#define MBD_SF_P(BB)                 \
+  switch (geo.p) {                   \
+    case 4: MBD_SF(4, BB); break;    \
+    case 6: MBD_SF(6, BB); break;    \
+    case 8: MBD_SF(8, BB); break;    \
+  }
+  switch (BG) {
+    case 1: MBD_SF_P(1); break;
+    case 2: MBD_SF_P(2); break;
+    case 4: MBD_SF_P(4); break;
+    case 8: MBD_SF_P(8); break;
+    case 16: MBD_SF_P(16); break;
+    case 32: MBD_SF_P(32); break;
+    case 64: MBD_SF_P(64); break;
+  }
+#undef MBD_SF_P
+#undef MBD_SF
+}
+
+template void launch_spme_force<float>(const Geometry&, const SysBuffers&, const void*, int, int,
+                                       int, hipStream_t);
+template void launch_spme_force<double>(const Geometry&, const SysBuffers&, const void*, int,
+                                        int, int, hipStream_t);
 
 template void launch_spread<float>(const Geometry&, const SysBuffers&, int, int, int, int,
                                    hipStream_t);

@@ -25,7 +25,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(L.LIB_PATH),
 def _declared(header):
     text = open(os.path.join(ROOT, "include", header)).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(mbdh?_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(mbdh?_[a-z_0-9]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -92,7 +92,8 @@ def _create(s, p, nsys=1):
     (lambda s, p: setattr(p, "block", 3), L.MBD_E_ARG),
     (lambda s, p: setattr(p, "precision", 7), L.MBD_E_ARG),
     (lambda s, p: setattr(p, "reorth", 9), L.MBD_E_ARG),
-    (lambda s, p: setattr(p, "want_forces", 1), L.MBD_E_ARG),
+    (lambda s, p: setattr(p, "want_forces", 2), L.MBD_E_ARG),
+    (lambda s, p: (setattr(p, "want_forces", 1), setattr(p, "block", 2)), L.MBD_E_ARG),
     (lambda s, p: setattr(s, "n_atoms", 0), L.MBD_E_ARG),
     (lambda s, p: setattr(s, "pos", None), L.MBD_E_ARG),
     (lambda s, p: s.cell.__setitem__(1, 0.5), L.MBD_E_CELL),
@@ -208,3 +209,61 @@ def test_hostcheck_tridiagonal_flags_indefinite():
     h.mbdh_tridiag_quadrature((C.c_double * 3)(*a), (C.c_double * 2)(*b), 3, C.byref(q),
                               C.byref(tmin))
     assert tmin.value < 0
+
+
+@pytest.mark.parametrize("p", [4, 6, 8])
+def test_hostcheck_bspline_second_derivative(p):
+    """M_p'' from the kernels' recursion against central differences of the oracle's M_p'."""
+    h = L.hostcheck()
+    th, dth, ddth = (C.c_double * p)(), (C.c_double * p)(), (C.c_double * p)()
+    eps = 1e-6
+    # away from the knots, where M_p''' (p = 4) jumps and central differences lose O(eps)
+    for w in (0.13, 0.27, 0.5, 0.93):
+        assert h.mbdh_bspline2(p, w, th, dth, ddth) == 0
+        x = torch.tensor([w + t for t in range(p)], dtype=torch.float64)
+        fd = (osp.bspline_deriv(p, x + eps) - osp.bspline_deriv(p, x - eps)) / (2 * eps)
+        assert np.allclose(list(ddth), fd.numpy(), atol=1e-8)
+        assert np.allclose(list(th), osp.bspline(p, x).numpy(), atol=1e-15)
+        assert np.allclose(list(dth), osp.bspline_deriv(p, x).numpy(), atol=1e-14)
+
+
+def test_hostcheck_direct_kernel_radial_derivatives():
+    """A'(r)/r and B'(r)/r of the direct-space kernel against autograd of the oracle's
+    radial functions."""
+    h = L.hostcheck()
+    A, B, dA, dB = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+    tau, d = 0.2223, 6.0
+    for S in (5.15, 5.98):
+        for r in np.concatenate([np.linspace(1.6, 4.0, 7), np.linspace(4.0, 25.0, 15)]):
+            h.mbdh_direct_kernel_grad(r * r, tau, 1.0 / S, d, C.byref(A), C.byref(B),
+                                      C.byref(dA), C.byref(dB))
+            rt = torch.tensor([r], dtype=torch.float64, requires_grad=True)
+            Ao, Bo = otz.radial_direct(rt, tau, torch.tensor([S], dtype=torch.float64), d)
+            (gA,) = torch.autograd.grad(Ao.sum(), rt, retain_graph=True)
+            (gB,) = torch.autograd.grad(Bo.sum(), rt)
+            sa = abs(float(gA[0])) / r + 1e-12 / r ** 4
+            sb = abs(float(gB[0])) / r + 1e-12 / r ** 6
+            assert dA.value == pytest.approx(float(gA[0]) / r, rel=1e-9, abs=1e-9 * sa), r
+            assert dB.value == pytest.approx(float(gB[0]) / r, rel=1e-9, abs=1e-9 * sb), r
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 30])
+def test_hostcheck_tridiagonal_adjoint_matches_autograd(n):
+    """dQ/da_k and dQ/db_k of the Gauss quadrature (tridiagonal eigenvectors plus
+    Daleckii-Krein divided differences) against autograd through the oracle's eigh."""
+    h = L.hostcheck()
+    rng = np.random.default_rng(100 + n)
+    a = rng.uniform(0.2, 0.6, n)
+    b = rng.uniform(0.01, 0.1, max(n - 1, 0))
+    ab, bb = (C.c_double * n)(), (C.c_double * n)()
+    ok = h.mbdh_tridiag_adjoint((C.c_double * n)(*a), (C.c_double * max(n - 1, 1))(*b), n,
+                                ab, bb)
+    assert ok == 1
+    at = torch.tensor(a, requires_grad=True)
+    bt = torch.tensor(b, requires_grad=True)
+    q, _, _ = olz.quadrature(at, bt)
+    grads = torch.autograd.grad(q, [at, bt] if n > 1 else [at])
+    assert np.allclose(list(ab), grads[0].numpy(), rtol=1e-9, atol=1e-12)
+    assert bb[0] == 0.0
+    if n > 1:
+        assert np.allclose(list(bb)[1:], grads[1].numpy(), rtol=1e-9, atol=1e-12)
