@@ -12,7 +12,10 @@ quadrature and energy in float64 ("mixed").
 Prints one JSON line on stdout; progress goes to stderr.
   metric  probe-vector SPME matvecs per second (batched, mixed precision)
   extra   plain one-vector float64 rate on the same GPU, the speedup, per-stage
-          times, the roofline of the dominant kernel and the CPU oracle rate.
+          times, the roofline of the dominant kernel, the CPU oracle rate, and the
+          E_MBD + forces wall time of the 12k-atom organic box (K=80, 64 probes x 40
+          steps, mixed); with --uneven also of the batch of 32 water boxes of
+          log-uniform size (500..20000 atoms, 64 probes x 40 steps each).
 """
 import argparse
 import json
@@ -77,6 +80,51 @@ def stage_bytes(stage, K, N, B):
     return None if per is None else per * B
 
 
+def energy_forces_leg(P, torch, synth, name):
+    """E_MBD + forces wall time (set_positions + execute with forces) for one workload,
+    next to the energy-only time of the same plan; one warm-up run first."""
+    wl = synth.workload(name)
+    A = synth.ANGSTROM_BOHR
+    grid = tuple(wl.grid) * 3 if wl.grid and len(wl.grid) == 1 else (0, 0, 0)
+    ds = [P.DeviceSystem(x.pos, x.cell, x.alpha, x.omega, x.rvdw) for x in wl.systems]
+    prm = P.Params(real_cutoff=wl.real_cutoff_angstrom * A, grid=grid, n_probes=wl.n_probes,
+                   n_steps=wl.n_steps, block=wl.block, precision=P.PREC_MIXED,
+                   seed=wl.probe_seed, want_forces=True)
+    plan = P.Plan(ds, prm)
+    pos = [d.pos.clone() for d in ds]
+
+    def run(forces):
+        for k, p in enumerate(pos):
+            plan.set_positions(p, k)
+        return plan.execute(forces=forces)
+
+    run(True)
+    torch.cuda.synchronize()
+    plan.check()
+    plan.stage_times()
+    plan.set_timing(True)
+    t0 = time.perf_counter()
+    e, f = run(True)
+    torch.cuda.synchronize()
+    t_ef = time.perf_counter() - t0
+    plan.set_timing(False)
+    stages = plan.stage_times()
+    t0 = time.perf_counter()
+    run(False)
+    torch.cuda.synchronize()
+    t_e = time.perf_counter() - t0
+    plan.check()
+    n_atoms = sum(x.n for x in wl.systems)
+    ok = bool(torch.isfinite(f).all())
+    plan.close()
+    log(f"{name}: E+F {1000 * t_ef:.1f} ms, E only {1000 * t_e:.1f} ms")
+    return {"workload": name, "systems": len(wl.systems), "atoms": n_atoms,
+            "probes": wl.n_probes, "lanczos_steps": wl.n_steps, "block": wl.block,
+            "energy_forces_ms": round(1000 * t_ef, 2), "energy_only_ms": round(1000 * t_e, 2),
+            "forces_finite": ok,
+            "stage_ms": {k: round(v[0], 2) for k, v in stages.items() if v[1] > 0}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +135,10 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 B=1 leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 1 GiB device copy first (reference for HBM byte counters)")
+    ap.add_argument("--no-forces", action="store_true",
+                    help="skip the energy + forces leg (12k-atom organic box)")
+    ap.add_argument("--uneven", action="store_true",
+                    help="also time the uneven batch (32 water boxes, energy + forces)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -194,6 +246,9 @@ def main():
         plain.close()
         log(f"plain fp64 B=1: {plain_rate:.1f} matvecs/s")
 
+    forces_leg = None if args.no_forces else energy_forces_leg(P, torch, synth, "forces12k")
+    uneven_leg = energy_forces_leg(P, torch, synth, "uneven") if args.uneven else None
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import method as om
@@ -238,7 +293,10 @@ def main():
         "stage_ms_per_step": {k: round(v, 3) for k, v in stage_ms.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "energy_forces": forces_leg,
     }
+    if uneven_leg is not None:
+        out["energy_forces_uneven"] = uneven_leg
     print(json.dumps(out), flush=True)
 
 

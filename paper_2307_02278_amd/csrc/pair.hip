@@ -233,17 +233,18 @@ k_pair_build(const Geometry geo, const int* __restrict__ cell_start,
   }
 }
 
-// E_dir of one group per work-group: WPB wavefronts, one lane per right-hand
-// side (B = 64 WPB), or for B = 16, 32 one wavefront whose lanes split into
-// NSUB = 64 / B target subsets. Tensors of CH candidates at a time are staged in
-// LDS; the wave-uniform target mask skips out-of-range (target, source) pairs.
+// E_dir of one group per work-group: WPB wavefronts, each with 64 / NSUB right-hand
+// sides x NSUB target subsets (lane = rhs + BW * subset), so B = 64 WPB / NSUB. More
+// subsets give more wavefronts per group (small systems) and fewer target slots per
+// lane. Tensors of CH candidates at a time are staged in LDS; the wave-uniform target
+// mask skips out-of-range (target, source) pairs.
 template <typename R, int NSUB, int WPB>
 __global__ void __launch_bounds__(64 * WPB)
 k_pair_list(const Geometry geo, const int2* __restrict__ hdr, const R* __restrict__ Tg,
             const int* __restrict__ gcount, int cap, const R* __restrict__ dv,
             R* __restrict__ Ed, int B) {
   constexpr int NT = 64 * WPB;
-  constexpr int CH = 16 * WPB;        // candidates per LDS chunk
+  constexpr int CH = 16 * WPB < 64 ? 16 * WPB : 64;  // candidates per LDS chunk
   constexpr int KT = kGroup / NSUB;   // target slots per lane
   constexpr int BW = 64 / NSUB;       // right-hand sides per wavefront
   constexpr int W16 = (int)(kCandStride * sizeof(R) / 16);  // 16-byte words per candidate
@@ -252,7 +253,7 @@ k_pair_list(const Geometry geo, const int2* __restrict__ hdr, const R* __restric
   const R* Tl = reinterpret_cast<const R*>(Tl4);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int rhs = (tid >> 6) * 64 + lane % BW;
+  const int rhs = (tid >> 6) * BW + lane % BW;
   const int sub = lane / BW;
   // XCD-aware: contiguous ranges of groups per XCD (blocks are dealt round-robin)
   const int per = (gridDim.x + 7) / 8;
@@ -326,7 +327,7 @@ k_pair_force(const Geometry geo, const int2* __restrict__ hdr, const R* __restri
              const int* __restrict__ gcount, int cap, const R* __restrict__ pv,
              const R* __restrict__ qv, double* __restrict__ fsum, int B) {
   constexpr int NT = 64 * WPB;
-  constexpr int CH = 16 * WPB;
+  constexpr int CH = 16 * WPB < 64 ? 16 * WPB : 64;
   constexpr int KT = kGroup / NSUB;
   constexpr int NPASS = KT / TP;
   constexpr int BW = 64 / NSUB;
@@ -338,7 +339,7 @@ k_pair_force(const Geometry geo, const int2* __restrict__ hdr, const R* __restri
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const int lane = tid & 63;
-  const int rhs = wave * 64 + lane % BW;
+  const int rhs = wave * BW + lane % BW;
   const int sub = lane / BW;
   const int per = (gridDim.x + 7) / 8;
   const int group = (blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -475,6 +476,15 @@ long long count_pairs(const Geometry& g, const SysBuffers& b, hipStream_t st) {
 template long long count_pairs<float>(const Geometry&, const SysBuffers&, hipStream_t);
 template long long count_pairs<double>(const Geometry&, const SysBuffers&, hipStream_t);
 
+// Target subsets per wavefront for the list kernels: at least 64 / B (every lane
+// busy), doubled (up to 4) while the launch would have fewer than 4096 wavefronts
+// (4 per SIMD), so that small systems still fill the GPU.
+int pair_subsets(int ngroups, int B) {
+  int ns = B >= 64 ? 1 : 64 / B;
+  while (ns < 4 && (long)ngroups * B * ns / 64 < 4096) ns *= 2;
+  return ns;
+}
+
 template <typename R>
 void launch_pair(const Geometry& g, const SysBuffers& b, int B, hipStream_t st) {
   const R* loc = (const R*)b.loc;
@@ -496,13 +506,24 @@ void launch_pair(const Geometry& g, const SysBuffers& b, int B, hipStream_t st) 
   const int nblk = (ngroups + 7) / 8 * 8;
   const int2* H = b.pg_hdr;
   const R* T = (const R*)b.pg_T;
-  switch (B) {
-    case 16: k_pair_list<R, 4, 1><<<nblk, 64, 0, st>>>(g, H, T, b.pg_count, b.pg_cap, dv, Ed, B); break;
-    case 32: k_pair_list<R, 2, 1><<<nblk, 64, 0, st>>>(g, H, T, b.pg_count, b.pg_cap, dv, Ed, B); break;
-    case 64: k_pair_list<R, 1, 1><<<nblk, 64, 0, st>>>(g, H, T, b.pg_count, b.pg_cap, dv, Ed, B); break;
-    case 128: k_pair_list<R, 1, 2><<<nblk, 128, 0, st>>>(g, H, T, b.pg_count, b.pg_cap, dv, Ed, B); break;
-    default: k_pair_list<R, 1, 4><<<nblk, 256, 0, st>>>(g, H, T, b.pg_count, b.pg_cap, dv, Ed, B); break;
+  const int ns = pair_subsets(ngroups, B);
+#define MBD_PL(NS, WP) \
+  k_pair_list<R, NS, WP><<<nblk, 64 * WP, 0, st>>>(g, H, T, b.pg_count, b.pg_cap, dv, Ed, B)
+  switch (B * 16 + ns) {
+    case 16 * 16 + 4: MBD_PL(4, 1); break;
+    case 32 * 16 + 2: MBD_PL(2, 1); break;
+    case 32 * 16 + 4: MBD_PL(4, 2); break;
+    case 64 * 16 + 1: MBD_PL(1, 1); break;
+    case 64 * 16 + 2: MBD_PL(2, 2); break;
+    case 64 * 16 + 4: MBD_PL(4, 4); break;
+    case 128 * 16 + 1: MBD_PL(1, 2); break;
+    case 128 * 16 + 2: MBD_PL(2, 4); break;
+    case 128 * 16 + 4: MBD_PL(4, 8); break;
+    case 256 * 16 + 1: MBD_PL(1, 4); break;
+    case 256 * 16 + 2: MBD_PL(2, 8); break;
+    default: MBD_PL(4, 16); break;
   }
+#undef MBD_PL
 }
 
 template <typename R>
@@ -522,17 +543,25 @@ void launch_pair_force(const Geometry& g, const SysBuffers& b, int B, hipStream_
   const R* F = (const R*)b.pg_F;
   const R* p = (const R*)b.dv;
   const R* q = (const R*)b.dq;
-#define MBD_PF(NS, WP, TPV, TH)                                                    \
-  k_pair_force<R, NS, WP, TPV><<<nblk, TH, 0, st>>>(g, H, F, b.pg_count, b.pg_cap, p, q, \
-                                                    b.fsum, B)
-  switch (B) {
-    case 4: MBD_PF(16, 1, 1, 64); break;
-    case 8: MBD_PF(8, 1, 2, 64); break;
-    case 16: MBD_PF(4, 1, 4, 64); break;
-    case 32: MBD_PF(2, 1, 8, 64); break;
-    case 64: MBD_PF(1, 1, 8, 64); break;
-    case 128: MBD_PF(1, 2, 8, 128); break;
-    default: MBD_PF(1, 4, 8, 256); break;
+  const int ns = pair_subsets(ngroups, B);
+#define MBD_PF(NS, WP, TPV)                                                             \
+  k_pair_force<R, NS, WP, TPV><<<nblk, 64 * WP, 0, st>>>(g, H, F, b.pg_count, b.pg_cap, p, q, \
+                                                         b.fsum, B)
+  switch (B * 16 + ns) {
+    case 4 * 16 + 16: MBD_PF(16, 1, 1); break;
+    case 8 * 16 + 8: MBD_PF(8, 1, 2); break;
+    case 16 * 16 + 4: MBD_PF(4, 1, 4); break;
+    case 32 * 16 + 2: MBD_PF(2, 1, 8); break;
+    case 32 * 16 + 4: MBD_PF(4, 2, 4); break;
+    case 64 * 16 + 1: MBD_PF(1, 1, 8); break;
+    case 64 * 16 + 2: MBD_PF(2, 2, 8); break;
+    case 64 * 16 + 4: MBD_PF(4, 4, 4); break;
+    case 128 * 16 + 1: MBD_PF(1, 2, 8); break;
+    case 128 * 16 + 2: MBD_PF(2, 4, 8); break;
+    case 128 * 16 + 4: MBD_PF(4, 8, 4); break;
+    case 256 * 16 + 1: MBD_PF(1, 4, 8); break;
+    case 256 * 16 + 2: MBD_PF(2, 8, 8); break;
+    default: MBD_PF(4, 16, 4); break;
   }
 #undef MBD_PF
 }
