@@ -531,6 +531,32 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
       }
       check(hipGetLastError(), "setup launch");
     }
+    if (n_sys > 1) {
+      // Longest-processing-time assignment of systems to up to 4 streams; the cost of
+      // one system is taken as N + K1 K2 K3 (pair work and grid work per right-hand side).
+      const int ns = std::min(n_sys, 4);
+      plan.pool.resize(ns, nullptr);
+      plan.pool_done.resize(ns, nullptr);
+      for (int i = 0; i < ns; ++i) {
+        check(hipStreamCreateWithFlags(&plan.pool[i], hipStreamNonBlocking), "stream create");
+        check(hipEventCreateWithFlags(&plan.pool_done[i], hipEventDisableTiming), "event create");
+      }
+      check(hipEventCreateWithFlags(&plan.fork, hipEventDisableTiming), "event create");
+      std::vector<int> order(n_sys);
+      std::vector<double> cost(n_sys), load(ns, 0.0);
+      for (int i = 0; i < n_sys; ++i) {
+        const Geometry& g = plan.sys[i].geo;
+        order[i] = i;
+        cost[i] = (double)g.n + (double)g.K[0] * g.K[1] * g.K[2];
+      }
+      std::sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+      plan.sys_stream.assign(n_sys, 0);
+      for (int i : order) {
+        const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        plan.sys_stream[i] = j;
+        load[j] += cost[i];
+      }
+    }
   } catch (const std::bad_alloc&) {
     mbd_plan_destroy(handle);
     return fail(MBD_E_OOM, "device allocation failed");
@@ -611,11 +637,18 @@ mbd_status mbd_execute(mbd_plan plan, double* energy, double* forces) {
   Plan& P = plan->plan;
   if (forces && !P.forces)
     return fail(MBD_E_STATE, "forces requested from a plan created with want_forces = 0");
+  const hipStream_t caller = P.stream;
   try {
-    check(hipMemsetAsync(P.status, 0, sizeof(uint32_t), P.stream), "clear status");
+    check(hipMemsetAsync(P.status, 0, sizeof(uint32_t), caller), "clear status");
+    const bool fork = !P.pool.empty();
+    if (fork) {
+      check(hipEventRecord(P.fork, caller), "fork");
+      for (hipStream_t q : P.pool) check(hipStreamWaitEvent(q, P.fork, 0), "fork");
+    }
     size_t off = 0;
     for (int s = 0; s < (int)P.sys.size(); ++s) {
       System& S = P.sys[s];
+      if (fork) P.stream = P.pool[P.sys_stream[s]];  // this system's work goes to its stream
       if (forces) fill_double(S.buf.fsum, 0.0, 3 * (size_t)S.geo.n, P.stream);
       if (P.prec == MBD_PREC_FP64) run_energy<double>(P, S, s, energy + s, forces != nullptr);
       else run_energy<float>(P, S, s, energy + s, forces != nullptr);
@@ -625,8 +658,15 @@ mbd_status mbd_execute(mbd_plan plan, double* energy, double* forces) {
         });
       off += (size_t)S.geo.n;
     }
+    P.stream = caller;
+    if (fork)
+      for (size_t i = 0; i < P.pool.size(); ++i) {
+        check(hipEventRecord(P.pool_done[i], P.pool[i]), "join");
+        check(hipStreamWaitEvent(caller, P.pool_done[i], 0), "join");
+      }
     check(hipGetLastError(), "execute launch");
   } catch (const HipError& e) {
+    P.stream = caller;
     return fail(MBD_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
   }
   P.executed = true;
@@ -708,7 +748,14 @@ mbd_status mbd_get_quadrature(mbd_plan plan, int32_t sys, double* q) {
 mbd_status mbd_plan_destroy(mbd_plan plan) {
   if (!plan) return MBD_OK;
   hipStreamSynchronize(plan->plan.stream);
+  for (hipStream_t q : plan->plan.pool)
+    if (q) hipStreamSynchronize(q);
   for (hipEvent_t e : plan->plan.timer.pool) hipEventDestroy(e);
+  for (hipEvent_t e : plan->plan.pool_done)
+    if (e) hipEventDestroy(e);
+  if (plan->plan.fork) hipEventDestroy(plan->plan.fork);
+  for (hipStream_t q : plan->plan.pool)
+    if (q) hipStreamDestroy(q);
   for (void* p : plan->plan.allocations) hipFree(p);
   delete plan;
   return MBD_OK;

@@ -156,6 +156,12 @@ struct Plan {
   bool executed = false;
   std::vector<void*> allocations;
   StageTimer timer;
+  // Batches of several systems run concurrently on internal streams (default
+  // priority), forked from and joined back to `stream` with events.
+  std::vector<hipStream_t> pool;
+  std::vector<hipEvent_t> pool_done;
+  hipEvent_t fork = nullptr;
+  std::vector<int> sys_stream;   // internal stream of each system
 };
 
 // ---------------------------------------------------------------------------

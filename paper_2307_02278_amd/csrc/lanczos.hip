@@ -323,31 +323,124 @@ __global__ void k_unpack(int n, int nrhs, int B, const int* __restrict__ perm,
 // Re-orthogonalization corrections are not differentiated.
 // ---------------------------------------------------------------------------
 
-// Per probe: eigenvectors of its tridiagonal and the quadrature adjoint.
-__global__ void k_tridiag_adjoint(int nb, int m, int probe0, const double* __restrict__ a,
-                                  const double* __restrict__ nrm, const int* __restrict__ meff,
-                                  double* __restrict__ tz, double* __restrict__ abar,
-                                  double* __restrict__ bbar, uint32_t* __restrict__ status) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nb) return;
+// Per probe (one 64-lane work-group each): eigenvectors of its tridiagonal by the
+// implicit symmetric QR iteration with Wilkinson shift, then the quadrature adjoint
+// dQ/dT = U (F o c c^T) U^T, c = U^T e1, F_ij = 1 / (sqrt(theta_i) + sqrt(theta_j)).
+// Lane 0 deflates and computes the Givens rotations of one sweep into LDS; every lane
+// then applies them to its own rows of U (rows never move between lanes, so no other
+// synchronization is needed). The adjoint's O(m^3) sums are split over the lanes.
+__global__ void __launch_bounds__(64)
+k_tridiag_adjoint(int m, int probe0, const double* __restrict__ a,
+                  const double* __restrict__ nrm, const int* __restrict__ meff,
+                  double* __restrict__ tz, double* __restrict__ abar, double* __restrict__ bbar,
+                  uint32_t* __restrict__ status) {
+  __shared__ double d[kMaxSteps], e[kMaxSteps], cs[kMaxSteps], sn[kMaxSteps];
+  __shared__ int ctl[3];  // lo, hi, state (0 sweep, 1 done, 2 no convergence)
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x;
   const int l = probe0 + b;
-  double d[kMaxSteps], e[kMaxSteps], work[2 * kMaxSteps];
   const int n = meff[l];
-  for (int k = 0; k < n; ++k) {
-    d[k] = a[l * m + k];
-    e[k] = (k + 1 < n) ? nrm[l * m + k + 1] : 0.0;
-  }
   double* u = tz + (size_t)b * m * m;
   double* ab = abar + (size_t)b * m;
   double* bb = bbar + (size_t)b * m;
-  for (int k = 0; k < m; ++k) ab[k] = bb[k] = 0.0;
-  if (!tridiag_eigen(d, e, u, n, m)) {
-    atomicOr(status, kErrNoConverge);
+  for (int k = lane; k < m; k += 64) {
+    ab[k] = 0.0;
+    bb[k] = 0.0;
+    if (k < n) {
+      d[k] = a[l * m + k];
+      e[k] = (k + 1 < n) ? nrm[l * m + k + 1] : 0.0;
+    }
+  }
+  for (int i = lane; i < n; i += 64)
+    for (int k = 0; k < n; ++k) u[(size_t)i * m + k] = (i == k) ? 1.0 : 0.0;
+  if (lane == 0) ctl[1] = n - 1;
+  __syncthreads();
+  const double eps = 2.220446049250313e-16;
+  int iter = 0;
+  while (true) {
+    if (lane == 0) {
+      int hi = ctl[1], st = 0;
+      while (hi > 0 && fabs(e[hi - 1]) <= eps * (fabs(d[hi - 1]) + fabs(d[hi]))) {
+        e[hi - 1] = 0.0;
+        --hi;
+      }
+      if (hi <= 0) {
+        st = 1;
+      } else if (++iter > 60 * n) {
+        st = 2;
+      } else {
+        int lo = hi - 1;
+        while (lo > 0 && fabs(e[lo - 1]) > eps * (fabs(d[lo - 1]) + fabs(d[lo]))) --lo;
+        const double delta = 0.5 * (d[hi - 1] - d[hi]);
+        const double eh = e[hi - 1];
+        const double den = delta + (delta >= 0.0 ? 1.0 : -1.0) * sqrt(delta * delta + eh * eh);
+        const double mu = (den != 0.0) ? d[hi] - eh * eh / den : d[hi];
+        double x = d[lo] - mu;
+        double z = e[lo];
+        for (int k = lo; k < hi; ++k) {
+          const double r = hypot(x, z);
+          double c = 1.0, sg = 0.0;
+          if (r != 0.0) { c = x / r; sg = -z / r; }
+          if (k > lo) e[k - 1] = r;
+          const double dk = d[k], dk1 = d[k + 1], ek = e[k];
+          d[k] = c * c * dk - 2.0 * c * sg * ek + sg * sg * dk1;
+          d[k + 1] = sg * sg * dk + 2.0 * c * sg * ek + c * c * dk1;
+          e[k] = c * sg * (dk - dk1) + (c * c - sg * sg) * ek;
+          if (k + 1 < hi) {
+            z = -sg * e[k + 1];
+            e[k + 1] = c * e[k + 1];
+            x = e[k];
+          }
+          cs[k] = c;
+          sn[k] = sg;
+        }
+        ctl[0] = lo;
+      }
+      ctl[1] = hi;
+      ctl[2] = st;
+    }
+    __syncthreads();
+    const int st = ctl[2];
+    if (st != 0) break;
+    const int lo = ctl[0], hi = ctl[1];
+    for (int i = lane; i < n; i += 64) {
+      double* ui = u + (size_t)i * m;
+      for (int k = lo; k < hi; ++k) {
+        const double a0 = ui[k], a1 = ui[k + 1];
+        ui[k] = cs[k] * a0 - sn[k] * a1;
+        ui[k + 1] = sn[k] * a0 + cs[k] * a1;
+      }
+    }
+    __syncthreads();
+  }
+  if (ctl[2] == 2) {
+    if (lane == 0) atomicOr(status, kErrNoConverge);
     return;
   }
-  for (int k = 0; k < n; ++k)
+  // eigenvalues d, eigenvectors in the columns of u; sqrt(theta) into cs
+  for (int k = lane; k < n; k += 64) {
     if (!(d[k] > 0.0)) atomicOr(status, kErrNotPosdef);
-  tridiag_sqrt_adjoint(d, u, n, m, work, ab, bb);
+    cs[k] = sqrt(d[k] > 0.0 ? d[k] : 0.0);
+  }
+  __syncthreads();
+  const double* c0 = u;  // first row: c_j = U_0j
+  for (int k = lane; k < n; k += 64) {
+    const double* uk = u + (size_t)k * m;
+    const double* ukm = k > 0 ? u + (size_t)(k - 1) * m : uk;
+    double mkk = 0.0, mkm = 0.0;
+    for (int i = 0; i < n; ++i) {
+      double acc = 0.0;
+      for (int j = 0; j < n; ++j) {
+        const double den = cs[i] + cs[j];
+        acc += (den > 0.0 ? 1.0 / den : 0.0) * c0[j] * uk[j];
+      }
+      const double v = acc * c0[i];
+      mkk += uk[i] * v;
+      mkm += ukm[i] * v;
+    }
+    ab[k] = mkk;
+    bb[k] = k > 0 ? 2.0 * mkm : 0.0;
+  }
 }
 
 // Five dot products per right-hand side into partial slots 0..4:
@@ -598,8 +691,8 @@ void fill_double(double* p, double v, size_t n, hipStream_t st) {
 
 void launch_tridiag_adjoint(const SysBuffers& b, int nb, int m, int probe0, uint32_t* status,
                             hipStream_t st) {
-  k_tridiag_adjoint<<<(nb + 31) / 32, 32, 0, st>>>(nb, m, probe0, b.a, b.b, b.meff, b.tz,
-                                                   b.abar, b.bbar, status);
+  k_tridiag_adjoint<<<nb, 64, 0, st>>>(m, probe0, b.a, b.b, b.meff, b.tz, b.abar, b.bbar,
+                                       status);
 }
 
 // One reverse step k: dots, scalars and the element-wise update, which leaves lbar_k in
