@@ -110,7 +110,7 @@ k_pair_build(const Geometry geo, const int* __restrict__ cell_start,
              int* __restrict__ gcount, int* __restrict__ maxcount) {
   __shared__ R tgt_all[4][kGroup][4];
   __shared__ int tcell_all[4][kGroup][3];
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int lane = threadIdx.x & 63;
   const int group = blockIdx.x * 4 + wave;
   const int g0 = group * kGroup;
@@ -288,14 +288,23 @@ k_pair_list(const Geometry geo, const int2* __restrict__ hdr, const R* __restric
         n0 = dj[0]; n1 = dj[B]; n2 = dj[2 * B];
       }
       const R* Tc = Tl + c * kCandStride + sub * kTensorWords;
+      // masked slots only (the kernel is close to the LDS read bandwidth); the sums
+      // go into the accumulators as fused multiply-add chains
 #pragma unroll
       for (int k = 0; k < KT; ++k) {
         if ((msk >> (k * NSUB)) & ((1u << NSUB) - 1u)) {
           const R* t = Tc + k * NSUB * kTensorWords;
           const R txx = t[0], tyy = t[1], tzz = t[2], txy = t[3], txz = t[4], tyz = t[5];
-          acc[k][0] += txx * d0 + txy * d1 + txz * d2;
-          acc[k][1] += txy * d0 + tyy * d1 + tyz * d2;
-          acc[k][2] += txz * d0 + tyz * d1 + tzz * d2;
+          R* a = acc[k];
+          a[0] = fma(txx, d0, a[0]);
+          a[0] = fma(txy, d1, a[0]);
+          a[0] = fma(txz, d2, a[0]);
+          a[1] = fma(txy, d0, a[1]);
+          a[1] = fma(tyy, d1, a[1]);
+          a[1] = fma(tyz, d2, a[1]);
+          a[2] = fma(txz, d0, a[2]);
+          a[2] = fma(tyz, d1, a[2]);
+          a[2] = fma(tzz, d2, a[2]);
         }
       }
     }

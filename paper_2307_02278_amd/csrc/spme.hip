@@ -45,11 +45,11 @@ k_spread(const Geometry geo, const int* __restrict__ tile_start,
   constexpr int NP = T * T * T / NSUB;  // points per lane
   constexpr int NWT = 6 * T;            // staged weights per atom: w, dw along x, y, z
   __shared__ R wts_all[4][64][NWT];
-  __shared__ int4 sat_all[4][64];       // atom, stencil offsets (o_x, o_y, o_z)
-  const int wave = threadIdx.x >> 6;
+  __shared__ int sat_all[4][64];        // atom index of each staged slot
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int lane = threadIdx.x & 63;
   R(*wts)[NWT] = wts_all[wave];
-  int4* sat = sat_all[wave];
+  int* sat = sat_all[wave];
   const int ntiles = geo.tiles[0] * geo.tiles[1] * geo.tiles[2];
   // Blocks are dealt round-robin to the 8 XCDs (gridDim.x is a multiple of 8):
   // each XCD takes one contiguous range of tiles, a slab of the grid, so the
@@ -93,25 +93,20 @@ k_spread(const Geometry geo, const int* __restrict__ tile_start,
           wts[lane][(2 * ax) * T + q] = v ? thp[ax * P + t] : R(0);
           wts[lane][(2 * ax + 1) * T + q] = v ? dthp[ax * P + t] : R(0);
         }
-      sat[lane] = make_int4(s, o[0], o[1], o[2]);
+      sat[lane] = s;
     }
     // the batch's LDS writes are visible to the whole wavefront before it reads them
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    int4 at = sat[0];
-    int s = __builtin_amdgcn_readfirstlane(at.x);
+    int s = __builtin_amdgcn_readfirstlane(sat[0]);
     R n0 = dv[((size_t)s * 3 + 0) * B + bg];
     R n1 = dv[((size_t)s * 3 + 1) * B + bg];
     R n2 = dv[((size_t)s * 3 + 2) * B + bg];
     for (int a = 0; a < na; ++a) {
-      const int ox = __builtin_amdgcn_readfirstlane(at.y);
-      const int oy = __builtin_amdgcn_readfirstlane(at.z);
-      const int oz = __builtin_amdgcn_readfirstlane(at.w);
       const R d0 = n0, d1 = n1, d2 = n2;
       if (a + 1 < na) {  // next atom's dipoles while this one is spread
-        at = sat[a + 1];
-        s = __builtin_amdgcn_readfirstlane(at.x);
+        s = __builtin_amdgcn_readfirstlane(sat[a + 1]);
         n0 = dv[((size_t)s * 3 + 0) * B + bg];
         n1 = dv[((size_t)s * 3 + 1) * B + bg];
         n2 = dv[((size_t)s * 3 + 2) * B + bg];
@@ -125,19 +120,19 @@ k_spread(const Geometry geo, const int* __restrict__ tile_start,
         wz[q] = wa[4 * T + q]; dwz[q] = wa[5 * T + q];
       }
       if (NSUB == 1) {
-        // uniform point loop: skip rows and points outside the atom's stencil
+        // every point of the tile: the staged weights are zero outside the stencil, and
+        // a branch-free loop issues fewer instructions than uniform per-point tests
 #pragma unroll
         for (int pz = 0; pz < T; ++pz) {
-          if (oz - pz < 0 || oz - pz >= P) continue;
 #pragma unroll
           for (int py = 0; py < T; ++py) {
-            if (oy - py < 0 || oy - py >= P) continue;
             const R A = d0 * wy[py] * wz[pz];
             const R Bc = d1 * dwy[py] * wz[pz] + d2 * wy[py] * dwz[pz];
 #pragma unroll
             for (int px = 0; px < T; ++px) {
-              if (ox - px < 0 || ox - px >= P) continue;
-              acc[(pz * T + py) * T + px] += dwx[px] * A + wx[px] * Bc;
+              R& q = acc[(pz * T + py) * T + px];
+              q = fma(dwx[px], A, q);
+              q = fma(wx[px], Bc, q);
             }
           }
         }
@@ -176,7 +171,7 @@ k_gather_epilogue(const Geometry geo, const int* __restrict__ base, const R* __r
                   double* __restrict__ part, int chunk0) {
   constexpr int NSUB = Lanes<BG>::NSUB;
   __shared__ double red[256];
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int lane = threadIdx.x & 63;
   const int b = lane % BG;
   const int sub = lane / BG;
@@ -288,7 +283,7 @@ k_spme_force(const Geometry geo, const int* __restrict__ base, const R* __restri
              size_t chunk_elems, const R* __restrict__ hv, int B, int chunk0,
              double* __restrict__ fsum) {
   constexpr int NSUB = Lanes<BG>::NSUB;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int lane = threadIdx.x & 63;
   const int b = lane % BG;
   const int sub = lane / BG;
