@@ -80,7 +80,7 @@ def stage_bytes(stage, K, N, B):
     return None if per is None else per * B
 
 
-def energy_forces_leg(P, torch, synth, name):
+def energy_forces_leg(P, torch, synth, name, graph):
     """E_MBD + forces wall time (set_positions + execute with forces) for one workload,
     next to the energy-only time of the same plan; one warm-up run first."""
     wl = synth.workload(name)
@@ -89,7 +89,7 @@ def energy_forces_leg(P, torch, synth, name):
     ds = [P.DeviceSystem(x.pos, x.cell, x.alpha, x.omega, x.rvdw) for x in wl.systems]
     prm = P.Params(real_cutoff=wl.real_cutoff_angstrom * A, grid=grid, n_probes=wl.n_probes,
                    n_steps=wl.n_steps, block=wl.block, precision=P.PREC_MIXED,
-                   seed=wl.probe_seed, want_forces=True)
+                   seed=wl.probe_seed, want_forces=True, graph=graph)
     plan = P.Plan(ds, prm)
     pos = [d.pos.clone() for d in ds]
 
@@ -99,27 +99,31 @@ def energy_forces_leg(P, torch, synth, name):
         return plan.execute(forces=forces)
 
     run(True)
+    run(False)
     torch.cuda.synchronize()
     plan.check()
-    plan.stage_times()
-    plan.set_timing(True)
     t0 = time.perf_counter()
     e, f = run(True)
     torch.cuda.synchronize()
     t_ef = time.perf_counter() - t0
-    plan.set_timing(False)
-    stages = plan.stage_times()
     t0 = time.perf_counter()
     run(False)
     torch.cuda.synchronize()
     t_e = time.perf_counter() - t0
     plan.check()
+    # per-stage times from one more (eager, event-timed) run
+    plan.stage_times()
+    plan.set_timing(True)
+    run(True)
+    plan.set_timing(False)
+    stages = plan.stage_times()
     n_atoms = sum(x.n for x in wl.systems)
     ok = bool(torch.isfinite(f).all())
     plan.close()
     log(f"{name}: E+F {1000 * t_ef:.1f} ms, E only {1000 * t_e:.1f} ms")
     return {"workload": name, "systems": len(wl.systems), "atoms": n_atoms,
             "probes": wl.n_probes, "lanczos_steps": wl.n_steps, "block": wl.block,
+            "graph": graph,
             "energy_forces_ms": round(1000 * t_ef, 2), "energy_only_ms": round(1000 * t_e, 2),
             "forces_finite": ok,
             "stage_ms": {k: round(v[0], 2) for k, v in stages.items() if v[1] > 0}}
@@ -139,6 +143,8 @@ def main():
                     help="skip the energy + forces leg (12k-atom organic box)")
     ap.add_argument("--uneven", action="store_true",
                     help="also time the uneven batch (32 water boxes, energy + forces)")
+    ap.add_argument("--eager", action="store_true",
+                    help="launch every kernel from the host instead of replaying HIP graphs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -157,7 +163,7 @@ def main():
     log(f"workload: water N={s.n} L={s.cell[0, 0] / A:.2f} A K={K} R={R} m={m} B={B}")
     ds = P.DeviceSystem(s.pos, s.cell, s.alpha, s.omega, s.rvdw)
     prm = P.Params(real_cutoff=wl.real_cutoff_angstrom * A, grid=K, n_probes=R, n_steps=m,
-                   block=B, precision=P.PREC_MIXED, seed=wl.probe_seed)
+                   block=B, precision=P.PREC_MIXED, seed=wl.probe_seed, graph=not args.eager)
     plan = P.Plan([ds], prm)
     info = plan.info(0)
     n_pairs = int(info.n_pairs)
@@ -200,6 +206,20 @@ def main():
     value = R * m * args.steps / dt
     log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.1f} matvecs/s, "
         f"E = {energy:.10e}")
+    graph_rate = None
+    if not args.eager:
+        # the same steps with execute replayed from its captured HIP graph
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            eg = step()
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - t0
+        plan.check()
+        assert float(eg[0]) == energy
+        graph_rate = R * m * args.steps / tg
+        log(f"graph replay: {1000 * tg / args.steps:.2f} ms/step, {graph_rate:.1f} matvecs/s")
 
     # Per-stage averages and the dominant kernel's roofline.
     stage_ms = {k: v[0] / args.steps for k, v in stages.items() if v[1] > 0}
@@ -246,8 +266,12 @@ def main():
         plain.close()
         log(f"plain fp64 B=1: {plain_rate:.1f} matvecs/s")
 
-    forces_leg = None if args.no_forces else energy_forces_leg(P, torch, synth, "forces12k")
-    uneven_leg = energy_forces_leg(P, torch, synth, "uneven") if args.uneven else None
+    graph = not args.eager
+    forces_leg = (None if args.no_forces
+                  else energy_forces_leg(P, torch, synth, "forces12k", graph))
+    # The uneven batch runs eagerly: its 32 systems overlap on 4 streams, which a replayed
+    # graph of that size did not keep (E+F 2.4 s replayed vs 2.1 s eager on one MI355X).
+    uneven_leg = energy_forces_leg(P, torch, synth, "uneven", False) if args.uneven else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -284,6 +308,7 @@ def main():
                                "128 probes x 50 Lanczos steps as one RHS block",
                    "n_atoms": s.n, "grid": list(K), "probes": R, "lanczos_steps": m,
                    "block": B, "pairs": n_pairs},
+        "graph_matvecs_per_s": round(graph_rate, 1) if graph_rate else None,
         "energy_ms": round(ms_per_step, 3),
         "energy_ha": energy,
         "plain_matvecs_per_s": round(plain_rate, 2) if plain_rate else None,

@@ -98,6 +98,11 @@ typedef struct {
                            can return forces (needs block >= 4); 0 => energy only      */
   int32_t deterministic;/* reserved: every reduction already runs in a fixed order, so
                            results are bit-reproducible run to run on one device        */
+  int32_t graph;        /* 1 => mbd_execute records its whole launch sequence (all
+                           systems, all streams) once into a HIP graph per variant
+                           (energy / energy + forces) and replays it afterwards; the
+                           positions may change between calls (mbd_set_positions).
+                           Stage timing (mbd_set_timing) runs eagerly instead.           */
 } mbd_params;
 
 /* Values derived on the host for one system of a plan. */

@@ -27,6 +27,7 @@ class Params:
     precision: int = L.PREC_FP64
     reorth: int = L.REORTH_NONE
     want_forces: bool = False
+    graph: bool = False             # replay execute from a captured HIP graph
 
     def to_c(self) -> L.MbdParams:
         p = L.MbdParams()
@@ -47,6 +48,7 @@ class Params:
         p.reorth = self.reorth
         p.want_forces = 1 if self.want_forces else 0
         p.deterministic = 0
+        p.graph = 1 if self.graph else 0
         return p
 
 

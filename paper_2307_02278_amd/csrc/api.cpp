@@ -421,6 +421,7 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
     return fail(MBD_E_ARG, "want_forces must be 0 or 1");
   if (prm.want_forces && prm.block < 4)
     return fail(MBD_E_ARG, "forces need block >= 4");
+  if (prm.graph != 0 && prm.graph != 1) return fail(MBD_E_ARG, "graph must be 0 or 1");
   for (int a = 0; a < 3; ++a)
     if (prm.grid[a] < 0) return fail(MBD_E_ARG, "grid sizes must be >= 0");
 
@@ -474,6 +475,7 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
   plan.B = prm.block;
   plan.BG = BG_plan;
   plan.forces = prm.want_forces != 0;
+  plan.use_graph = prm.graph != 0;
   plan.stream = static_cast<hipStream_t>(stream);
   hipGetDevice(&plan.device);
   try {
@@ -530,6 +532,15 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
         if (plan.B >= 16 || plan.forces) create_pair_list<float>(plan, S);
       }
       check(hipGetLastError(), "setup launch");
+    }
+    if (plan.use_graph) {
+      check(hipStreamCreateWithFlags(&plan.gstream, hipStreamNonBlocking), "stream create");
+      check(hipEventCreateWithFlags(&plan.g_in, hipEventDisableTiming), "event create");
+      check(hipEventCreateWithFlags(&plan.g_out, hipEventDisableTiming), "event create");
+      size_t nat = 0, gb = 0;
+      for (const auto& S : plan.sys) nat += (size_t)S.geo.n;
+      plan.e_out = dalloc<double>(plan, n_sys, gb);
+      if (plan.forces) plan.f_out = dalloc<double>(plan, 3 * nat, gb);
     }
     if (n_sys > 1) {
       // Longest-processing-time assignment of systems to up to 4 streams; the cost of
@@ -631,21 +642,21 @@ mbd_status mbd_get_stage_times(mbd_plan plan, double* ms, int64_t* launches) {
   return MBD_OK;
 }
 
-mbd_status mbd_execute(mbd_plan plan, double* energy, double* forces) {
-  using namespace mbd;
-  if (!plan || !energy) return fail(MBD_E_ARG, "NULL argument");
-  Plan& P = plan->plan;
-  if (forces && !P.forces)
-    return fail(MBD_E_STATE, "forces requested from a plan created with want_forces = 0");
+namespace mbd {
+namespace {
+
+// Enqueue one full evaluation (all systems) on plan.stream: clear the status word,
+// fork to the internal streams, run every system, join back.
+void enqueue_execute(Plan& P, double* energy, double* forces) {
   const hipStream_t caller = P.stream;
+  fill_int(reinterpret_cast<int*>(P.status), 0, 1, caller);
+  const bool fork = !P.pool.empty();
+  if (fork) {
+    check(hipEventRecord(P.fork, caller), "fork");
+    for (hipStream_t q : P.pool) check(hipStreamWaitEvent(q, P.fork, 0), "fork");
+  }
+  size_t off = 0;
   try {
-    check(hipMemsetAsync(P.status, 0, sizeof(uint32_t), caller), "clear status");
-    const bool fork = !P.pool.empty();
-    if (fork) {
-      check(hipEventRecord(P.fork, caller), "fork");
-      for (hipStream_t q : P.pool) check(hipStreamWaitEvent(q, P.fork, 0), "fork");
-    }
-    size_t off = 0;
     for (int s = 0; s < (int)P.sys.size(); ++s) {
       System& S = P.sys[s];
       if (fork) P.stream = P.pool[P.sys_stream[s]];  // this system's work goes to its stream
@@ -658,15 +669,67 @@ mbd_status mbd_execute(mbd_plan plan, double* energy, double* forces) {
         });
       off += (size_t)S.geo.n;
     }
+  } catch (...) {
     P.stream = caller;
-    if (fork)
-      for (size_t i = 0; i < P.pool.size(); ++i) {
-        check(hipEventRecord(P.pool_done[i], P.pool[i]), "join");
-        check(hipStreamWaitEvent(caller, P.pool_done[i], 0), "join");
+    throw;
+  }
+  P.stream = caller;
+  if (fork)
+    for (size_t i = 0; i < P.pool.size(); ++i) {
+      check(hipEventRecord(P.pool_done[i], P.pool[i]), "join");
+      check(hipStreamWaitEvent(caller, P.pool_done[i], 0), "join");
+    }
+}
+
+}  // namespace
+}  // namespace mbd
+
+mbd_status mbd_execute(mbd_plan plan, double* energy, double* forces) {
+  using namespace mbd;
+  if (!plan || !energy) return fail(MBD_E_ARG, "NULL argument");
+  Plan& P = plan->plan;
+  if (forces && !P.forces)
+    return fail(MBD_E_STATE, "forces requested from a plan created with want_forces = 0");
+  try {
+    if (!P.use_graph || P.timer.on) {
+      enqueue_execute(P, energy, forces);
+    } else {
+      const int gi = forces ? 1 : 0;
+      const hipStream_t caller = P.stream;
+      if (!P.gexec[gi]) {
+        hipGraph_t g = nullptr;
+        P.stream = P.gstream;  // the sequence is recorded from the plan's own stream
+        check(hipStreamBeginCapture(P.gstream, hipStreamCaptureModeRelaxed), "begin capture");
+        try {
+          enqueue_execute(P, P.e_out, forces ? P.f_out : nullptr);
+        } catch (...) {
+          P.stream = caller;
+          hipStreamEndCapture(P.gstream, &g);
+          if (g) hipGraphDestroy(g);
+          throw;
+        }
+        P.stream = caller;
+        check(hipStreamEndCapture(P.gstream, &g), "end capture");
+        const hipError_t e = hipGraphInstantiate(&P.gexec[gi], g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        check(e, "graph instantiate");
       }
+      // replay after the caller's earlier work; the caller's later work waits for it
+      check(hipEventRecord(P.g_in, caller), "graph fork");
+      check(hipStreamWaitEvent(P.gstream, P.g_in, 0), "graph fork");
+      check(hipGraphLaunch(P.gexec[gi], P.gstream), "graph launch");
+      check(hipEventRecord(P.g_out, P.gstream), "graph join");
+      check(hipStreamWaitEvent(caller, P.g_out, 0), "graph join");
+      size_t nat = 0;
+      for (const auto& S : P.sys) nat += (size_t)S.geo.n;
+      check(hipMemcpyAsync(energy, P.e_out, sizeof(double) * P.sys.size(),
+                           hipMemcpyDeviceToDevice, P.stream), "copy energy");
+      if (forces)
+        check(hipMemcpyAsync(forces, P.f_out, sizeof(double) * 3 * nat, hipMemcpyDeviceToDevice,
+                             P.stream), "copy forces");
+    }
     check(hipGetLastError(), "execute launch");
   } catch (const HipError& e) {
-    P.stream = caller;
     return fail(MBD_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
   }
   P.executed = true;
@@ -750,6 +813,12 @@ mbd_status mbd_plan_destroy(mbd_plan plan) {
   hipStreamSynchronize(plan->plan.stream);
   for (hipStream_t q : plan->plan.pool)
     if (q) hipStreamSynchronize(q);
+  if (plan->plan.gstream) hipStreamSynchronize(plan->plan.gstream);
+  for (hipGraphExec_t g : plan->plan.gexec)
+    if (g) hipGraphExecDestroy(g);
+  if (plan->plan.g_in) hipEventDestroy(plan->plan.g_in);
+  if (plan->plan.g_out) hipEventDestroy(plan->plan.g_out);
+  if (plan->plan.gstream) hipStreamDestroy(plan->plan.gstream);
   for (hipEvent_t e : plan->plan.timer.pool) hipEventDestroy(e);
   for (hipEvent_t e : plan->plan.pool_done)
     if (e) hipEventDestroy(e);

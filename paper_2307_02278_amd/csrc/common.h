@@ -162,6 +162,14 @@ struct Plan {
   std::vector<hipEvent_t> pool_done;
   hipEvent_t fork = nullptr;
   std::vector<int> sys_stream;   // internal stream of each system
+  // Graph replay of mbd_execute: [0] energy only, [1] energy + forces. Outputs of a
+  // replay land in plan-owned buffers and are copied to the caller's afterwards.
+  bool use_graph = false;
+  hipStream_t gstream = nullptr;  // capture and replay stream (the caller's may be the null stream)
+  hipEvent_t g_in = nullptr, g_out = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  double* e_out = nullptr;       // [n_sys]
+  double* f_out = nullptr;       // [sum n][3] (forces plans)
 };
 
 // ---------------------------------------------------------------------------

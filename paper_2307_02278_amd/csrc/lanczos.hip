@@ -235,19 +235,21 @@ __global__ void k_init_probe_scalars(int nb, int m, int probe0, double* __restri
   meff[l] = m;
 }
 
-// Gauss quadrature per probe from its tridiagonal (implicit QR, first-row tracking).
-__global__ void k_tridiag(int nb, int m, int probe0, const double* __restrict__ a,
-                          const double* __restrict__ nrm, const int* __restrict__ meff,
-                          double* __restrict__ q, uint32_t* __restrict__ status) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nb) return;
-  const int l = probe0 + b;
-  double d[kMaxSteps], e[kMaxSteps], z[kMaxSteps];
+// Gauss quadrature per probe from its tridiagonal (implicit QR, first-row tracking):
+// one work-group per probe, its working arrays in LDS (the iteration is sequential and
+// runs on lane 0; LDS instead of private arrays avoids scratch-memory latency).
+__global__ void __launch_bounds__(64)
+k_tridiag(int m, int probe0, const double* __restrict__ a, const double* __restrict__ nrm,
+          const int* __restrict__ meff, double* __restrict__ q, uint32_t* __restrict__ status) {
+  __shared__ double d[kMaxSteps], e[kMaxSteps], z[kMaxSteps];
+  const int l = probe0 + blockIdx.x;
   const int n = meff[l];
-  for (int k = 0; k < n; ++k) {
+  for (int k = threadIdx.x; k < n; k += 64) {
     d[k] = a[l * m + k];
     e[k] = (k + 1 < n) ? nrm[l * m + k + 1] : 0.0;
   }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   double tmin;
   int ok;
   const double v = tridiag_sqrt_quadrature(d, e, z, n, &tmin, &ok);
@@ -675,7 +677,7 @@ void launch_finish_norm(const SysBuffers& b, int B, int nb, int k, int m, int pr
 
 void launch_tridiag(const SysBuffers& b, int nb, int m, int probe0, uint32_t* status,
                     hipStream_t st) {
-  k_tridiag<<<(nb + 31) / 32, 32, 0, st>>>(nb, m, probe0, b.a, b.b, b.meff, b.q, status);
+  k_tridiag<<<nb, 64, 0, st>>>(m, probe0, b.a, b.b, b.meff, b.q, status);
 }
 
 void launch_energy(const Geometry& geo, const SysBuffers& b, int R, double* energy_out,
