@@ -327,28 +327,35 @@ k_pair_list(const Geometry geo, const int2* __restrict__ hdr, const R* __restric
 // r = R_j + n - R_t; with T_dir = A I - B r r^T, X = p_t.q_j + q_t.p_j and
 // Y = (p_t.r)(q_j.r) + (q_t.r)(p_j.r):
 //   grad_r u = r (A'/r X - B'/r Y) - B [p_t (q_j.r) + q_j (p_t.r) + q_t (p_j.r) + p_j (q_t.r)].
-// Same group and lane layout as k_pair_list; TP target slots per pass keep p_t and q_t
-// in registers. The sum over right-hand sides is reduced per target and added to
-// fsum (each group owns its targets: no atomics, fixed order).
-template <typename R, int NSUB, int WPB, int TP>
-__global__ void __launch_bounds__(64 * WPB)
+// Work-group per group: TW x RS wavefronts; wavefront (tw, rs) owns the targets
+// [tw 16/TW, (tw+1) 16/TW) and the right-hand sides [rs BW, (rs+1) BW) (BW = 64/NSUB,
+// NSUB > 1 only when B < 64), so the mask branch is uniform and no lane idles on an
+// out-of-range pair. TP target slots per pass keep p_t and q_t in registers. The sum
+// over right-hand sides is reduced per target and added to fsum (each group owns its
+// targets: no atomics, fixed order).
+template <typename R, int NSUB, int TW, int RS, int TP>
+__global__ void __launch_bounds__(64 * TW * RS)
 k_pair_force(const Geometry geo, const int2* __restrict__ hdr, const R* __restrict__ Fg,
              const int* __restrict__ gcount, int cap, const R* __restrict__ pv,
              const R* __restrict__ qv, double* __restrict__ fsum, int B) {
-  constexpr int NT = 64 * WPB;
-  constexpr int CH = 16 * WPB < 64 ? 16 * WPB : 64;
-  constexpr int KT = kGroup / NSUB;
+  constexpr int NT = 64 * TW * RS;
+  constexpr int CH = 16 * TW * RS < 64 ? 16 * TW * RS : 64;
+  constexpr int TPW = kGroup / TW;
+  constexpr int KT = TPW / NSUB;
   constexpr int NPASS = KT / TP;
   constexpr int BW = 64 / NSUB;
   constexpr int W16 = (int)(kCandStride * sizeof(R) / 16);
+  static_assert(KT >= 1 && KT * NSUB * TW == kGroup && NPASS * TP == KT, "bad split");
   __shared__ uint4 Fl4[CH * W16];
   __shared__ int2 hl[CH];
-  __shared__ double red[WPB][kGroup][3];
+  __shared__ double red[RS][kGroup][3];
   const R* Fl = reinterpret_cast<const R*>(Fl4);
   const int tid = threadIdx.x;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
-  const int rhs = wave * BW + lane % BW;
+  const int tw = wave % TW, rs = wave / TW;
+  const int t0 = tw * TPW;
+  const int rhs = rs * BW + lane % BW;
   const int sub = lane / BW;
   const int per = (gridDim.x + 7) / 8;
   const int group = (blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -361,7 +368,7 @@ k_pair_force(const Geometry geo, const int2* __restrict__ hdr, const R* __restri
     R pt[TP][3], qt[TP][3], G[TP][3];
 #pragma unroll
     for (int k = 0; k < TP; ++k) {
-      const int i = group * kGroup + (pass * TP + k) * NSUB + sub;
+      const int i = group * kGroup + t0 + (pass * TP + k) * NSUB + sub;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         pt[k][a] = i < geo.n ? pv[((size_t)i * 3 + a) * B + rhs] : R(0);
@@ -378,12 +385,12 @@ k_pair_force(const Geometry geo, const int2* __restrict__ hdr, const R* __restri
       for (int c = 0; c < nc; ++c) {
         const int2 h = hl[c];
         const int j = __builtin_amdgcn_readfirstlane(h.x);
-        const uint32_t msk = (uint32_t)__builtin_amdgcn_readfirstlane(h.y);
+        const uint32_t msk = (uint32_t)__builtin_amdgcn_readfirstlane(h.y) >> t0;
         const R* pj = pv + (size_t)j * 3 * B + rhs;
         const R* qj = qv + (size_t)j * 3 * B + rhs;
         const R p0 = pj[0], p1 = pj[B], p2 = pj[2 * B];
         const R q0 = qj[0], q1 = qj[B], q2 = qj[2 * B];
-        const R* Fc = Fl + c * kCandStride + sub * kTensorWords;
+        const R* Fc = Fl + c * kCandStride + (t0 + sub) * kTensorWords;
 #pragma unroll
         for (int k = 0; k < TP; ++k) {
           const int slot = pass * TP + k;
@@ -405,7 +412,7 @@ k_pair_force(const Geometry geo, const int2* __restrict__ hdr, const R* __restri
         }
       }
     }
-    // sum over the right-hand sides: the BW lanes of a target subset, then the waves
+    // sum over the right-hand sides: the BW lanes of a target subset, then the slices
 #pragma unroll
     for (int k = 0; k < TP; ++k) {
       double g0 = G[k][0], g1 = G[k][1], g2 = G[k][2];
@@ -414,19 +421,19 @@ k_pair_force(const Geometry geo, const int2* __restrict__ hdr, const R* __restri
         g1 += __shfl_xor(g1, off);
         g2 += __shfl_xor(g2, off);
       }
-      const int t = (pass * TP + k) * NSUB + sub;
+      const int t = t0 + (pass * TP + k) * NSUB + sub;
       if (lane % BW == 0) {
-        red[wave][t][0] = g0;
-        red[wave][t][1] = g1;
-        red[wave][t][2] = g2;
+        red[rs][t][0] = g0;
+        red[rs][t][1] = g1;
+        red[rs][t][2] = g2;
       }
     }
     __syncthreads();
     if (tid < kGroup * 3) {
       const int t = tid / 3, a = tid % 3;
-      if ((t / NSUB) / TP == pass) {  // target t was handled in this pass
+      if (((t % TPW) / NSUB) / TP == pass) {  // target t was handled in this pass
         double v = 0.0;
-        for (int w = 0; w < WPB; ++w) v += red[w][t][a];
+        for (int r = 0; r < RS; ++r) v += red[r][t][a];
         const int i = group * kGroup + t;
         if (i < geo.n) fsum[3 * (size_t)i + a] += v;
       }
@@ -552,25 +559,34 @@ void launch_pair_force(const Geometry& g, const SysBuffers& b, int B, hipStream_
   const R* F = (const R*)b.pg_F;
   const R* p = (const R*)b.dv;
   const R* q = (const R*)b.dq;
-  const int ns = pair_subsets(ngroups, B);
-#define MBD_PF(NS, WP, TPV)                                                             \
-  k_pair_force<R, NS, WP, TPV><<<nblk, 64 * WP, 0, st>>>(g, H, F, b.pg_count, b.pg_cap, p, q, \
-                                                         b.fsum, B)
-  switch (B * 16 + ns) {
-    case 4 * 16 + 16: MBD_PF(16, 1, 1); break;
-    case 8 * 16 + 8: MBD_PF(8, 1, 2); break;
-    case 16 * 16 + 4: MBD_PF(4, 1, 4); break;
-    case 32 * 16 + 2: MBD_PF(2, 1, 8); break;
-    case 32 * 16 + 4: MBD_PF(4, 2, 4); break;
-    case 64 * 16 + 1: MBD_PF(1, 1, 8); break;
-    case 64 * 16 + 2: MBD_PF(2, 2, 8); break;
-    case 64 * 16 + 4: MBD_PF(4, 4, 4); break;
-    case 128 * 16 + 1: MBD_PF(1, 2, 8); break;
-    case 128 * 16 + 2: MBD_PF(2, 4, 8); break;
-    case 128 * 16 + 4: MBD_PF(4, 8, 4); break;
-    case 256 * 16 + 1: MBD_PF(1, 4, 8); break;
-    case 256 * 16 + 2: MBD_PF(2, 8, 8); break;
-    default: MBD_PF(4, 16, 4); break;
+  // right-hand-side slices of 64 (or target subsets when B < 64), then target splits
+  // over 1-4 wavefronts until the launch has 4096 wavefronts
+  const int rs = B >= 64 ? B / 64 : 1;
+  const int nsub = B >= 64 ? 1 : 64 / B;  // lane subsets: at most 16 / nsub wavefronts
+  int tw = 1;
+  while (tw < 4 && tw * nsub < 16 && tw * rs < 16 && (long)ngroups * tw * rs < 4096) tw *= 2;
+#define MBD_PF(NS, TWV, RSV, TPV)                                                        \
+  k_pair_force<R, NS, TWV, RSV, TPV><<<nblk, 64 * TWV * RSV, 0, st>>>(                   \
+      g, H, F, b.pg_count, b.pg_cap, p, q, b.fsum, B)
+  switch (B * 16 + tw) {
+    case 4 * 16 + 1: MBD_PF(16, 1, 1, 1); break;
+    case 8 * 16 + 1: MBD_PF(8, 1, 1, 2); break;
+    case 8 * 16 + 2: MBD_PF(8, 2, 1, 1); break;
+    case 16 * 16 + 1: MBD_PF(4, 1, 1, 4); break;
+    case 16 * 16 + 2: MBD_PF(4, 2, 1, 2); break;
+    case 16 * 16 + 4: MBD_PF(4, 4, 1, 1); break;
+    case 32 * 16 + 1: MBD_PF(2, 1, 1, 8); break;
+    case 32 * 16 + 2: MBD_PF(2, 2, 1, 4); break;
+    case 32 * 16 + 4: MBD_PF(2, 4, 1, 2); break;
+    case 64 * 16 + 1: MBD_PF(1, 1, 1, 8); break;
+    case 64 * 16 + 2: MBD_PF(1, 2, 1, 8); break;
+    case 64 * 16 + 4: MBD_PF(1, 4, 1, 4); break;
+    case 128 * 16 + 1: MBD_PF(1, 1, 2, 8); break;
+    case 128 * 16 + 2: MBD_PF(1, 2, 2, 8); break;
+    case 128 * 16 + 4: MBD_PF(1, 4, 2, 4); break;
+    case 256 * 16 + 1: MBD_PF(1, 1, 4, 8); break;
+    case 256 * 16 + 2: MBD_PF(1, 2, 4, 8); break;
+    default: MBD_PF(1, 4, 4, 4); break;
   }
 #undef MBD_PF
 }

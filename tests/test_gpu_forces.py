@@ -58,10 +58,10 @@ def test_forces_fp64_match_oracle(tiny, block):
     assert err <= 1e-7 * float(f_ref.abs().max()), err
 
 
-@pytest.mark.parametrize("block", [16, 64])
+@pytest.mark.parametrize("block", [16, 64, 128])
 def test_forces_mixed_match_oracle(tiny, block):
     import paper_2307_02278_amd as P
-    R, m = 16, 12
+    R, m = 16, 12  # at block 128 the block is ragged (16 probes in flight)
     plan = _plan(tiny, P.PREC_MIXED, block, R, m)
     e, f = plan.execute(forces=True)
     plan.check()
