@@ -54,7 +54,7 @@ typedef int32_t mbd_status;
 enum {
   MBD_OK = 0,
   MBD_E_ARG = -1,         /* invalid argument (sizes, parameters, NULL pointers)          */
-  MBD_E_CELL = -2,        /* cell is not orthorhombic (only diagonal cells are supported)  */
+  MBD_E_CELL = -2,        /* cell vectors not right-handed, or degenerate (zero volume)     */
   MBD_E_GRID = -3,        /* grid size unsupported (see mbd_grid_supported) or < 2p        */
   MBD_E_NOT_POSDEF = -4,  /* a Ritz value theta_k <= 0: C is not positive definite         */
   MBD_E_NONFINITE = -5,   /* NaN/Inf met in a field, a Lanczos scalar or the energy        */
@@ -72,7 +72,7 @@ enum { MBD_C_DIAG = 1, MBD_C_DIR = 2, MBD_C_REC = 4, MBD_C_SELF = 8, MBD_C_ALL =
 typedef struct {
   int32_t n_atoms;      /* N >= 1                                                      */
   const double* pos;    /* device [N][3], bohr                                          */
-  double cell[9];       /* host copy, rows a1, a2, a3 in bohr; must be diagonal         */
+  double cell[9];       /* host copy, rows a1, a2, a3 in bohr (any right-handed cell)   */
   const double* alpha;  /* device [N], static polarizability alpha_i(0) > 0, bohr^3     */
   const double* omega;  /* device [N], characteristic frequency omega_i > 0, Hartree    */
   const double* r_vdw;  /* device [N], van der Waals radius > 0, bohr                   */

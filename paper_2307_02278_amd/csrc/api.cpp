@@ -52,6 +52,24 @@ int grid_rule(double L_bohr) {
 
 bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
+double cell_volume(const double (&A)[3][3]) {
+  return A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+         A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+         A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+}
+
+// Reciprocal vectors a*_a = (a_b x a_c) / V, (a, b, c) cyclic, so a*_a . a_b = delta_ab.
+void reciprocal(const double (&A)[3][3], double (&Ar)[3][3]) {
+  const double V = cell_volume(A);
+  for (int a = 0; a < 3; ++a) {
+    const double* u = A[(a + 1) % 3];
+    const double* v = A[(a + 2) % 3];
+    Ar[a][0] = (u[1] * v[2] - u[2] * v[1]) / V;
+    Ar[a][1] = (u[2] * v[0] - u[0] * v[2]) / V;
+    Ar[a][2] = (u[0] * v[1] - u[1] * v[0]) / V;
+  }
+}
+
 template <typename T>
 T* dalloc(Plan& plan, size_t count, size_t& bytes) {
   void* p = nullptr;
@@ -67,7 +85,7 @@ T* dalloc(Plan& plan, size_t count, size_t& bytes) {
 template <typename R>
 void host_tables(const Geometry& g, std::vector<R>& G, std::vector<R>& tw) {
   const int K1 = g.K[0], K2 = g.K[1], K3 = g.K[2], KX = K1 / 2 + 1;
-  const double V = g.L[0] * g.L[1] * g.L[2];
+  const double V = cell_volume(g.A);
   double th[kMaxOrder], dth[kMaxOrder];
   std::vector<double> Mk(g.p);
   switch (g.p) {
@@ -92,12 +110,16 @@ void host_tables(const Geometry& g, std::vector<R>& G, std::vector<R>& tw) {
   const auto b1 = bmod(K1), b2 = bmod(K2), b3 = bmod(K3);
   G.assign((size_t)K3 * K2 * KX, R(0));
   for (int kz = 0; kz < K3; ++kz) {
-    const double mz = (kz <= K3 / 2 ? kz : kz - K3) / g.L[2];
+    const double fz = (kz <= K3 / 2 ? kz : kz - K3);
     for (int ky = 0; ky < K2; ++ky) {
-      const double my = (ky <= K2 / 2 ? ky : ky - K2) / g.L[1];
+      const double fy = (ky <= K2 / 2 ? ky : ky - K2);
       for (int kx = 0; kx < KX; ++kx) {
-        const double mx = kx / g.L[0];
-        const double m2 = mx * mx + my * my + mz * mz;
+        // m = sum_a m_a a*_a (reciprocal lattice vector of the DFT index)
+        double m2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+          const double mc = kx * g.Ar[0][c] + fy * g.Ar[1][c] + fz * g.Ar[2][c];
+          m2 += mc * mc;
+        }
         double v = 0.0;
         if (m2 > 0.0)
           v = std::exp(-M_PI * M_PI * m2 / (g.tau * g.tau)) * b1[kx] * b2[ky] * b3[kz] /
@@ -369,7 +391,7 @@ const char* mbd_status_string(mbd_status s) {
   switch (s) {
     case MBD_OK: return "ok";
     case MBD_E_ARG: return "invalid argument";
-    case MBD_E_CELL: return "cell is not orthorhombic";
+    case MBD_E_CELL: return "invalid cell";
     case MBD_E_GRID: return "unsupported grid";
     case MBD_E_NOT_POSDEF: return "coupling matrix not positive definite";
     case MBD_E_NONFINITE: return "non-finite value";
@@ -434,16 +456,16 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
       return fail(MBD_E_ARG, "system arrays must be non-NULL device pointers");
     for (int i = 0; i < 9; ++i)
       if (!std::isfinite(sy.cell[i])) return fail(MBD_E_ARG, "cell is not finite");
-    for (int r = 0; r < 3; ++r)
-      for (int c = 0; c < 3; ++c)
-        if (r != c && sy.cell[3 * r + c] != 0.0)
-          return fail(MBD_E_CELL, "only orthorhombic (diagonal) cells are supported");
     Geometry& g = geos[s];
     g.n = sy.n_atoms;
-    for (int a = 0; a < 3; ++a) {
-      g.L[a] = sy.cell[4 * a];
-      if (!(g.L[a] > 0.0)) return fail(MBD_E_CELL, "cell edges must be > 0");
-    }
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) g.A[r][c] = sy.cell[3 * r + c];
+    const double vol = cell_volume(g.A);
+    for (int a = 0; a < 3; ++a)
+      g.L[a] = std::sqrt(g.A[a][0] * g.A[a][0] + g.A[a][1] * g.A[a][1] + g.A[a][2] * g.A[a][2]);
+    if (!(vol > 1e-6 * g.L[0] * g.L[1] * g.L[2]))
+      return fail(MBD_E_CELL, "cell vectors must be right-handed with a non-degenerate volume");
+    reciprocal(g.A, g.Ar);
     g.p = prm.spline_order;
     for (int a = 0; a < 3; ++a) {
       int K = prm.grid[a] > 0 ? prm.grid[a] : grid_rule(g.L[a]);
@@ -453,6 +475,8 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
       if (K < 2 * g.p) return fail(MBD_E_GRID, "grid must be >= 2 p");
       g.K[a] = K;
     }
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < 3; ++c) g.Mu[a][c] = g.K[a] * g.Ar[a][c];
     // Spread tiles: 4x4x4 grid points, one wavefront each.
     g.tile[0] = g.tile[1] = g.tile[2] = kSpreadTile;
     for (int a = 0; a < 3; ++a) g.tiles[a] = (g.K[a] + g.tile[a] - 1) / g.tile[a];
@@ -516,10 +540,16 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
       g.r_pair = rp;
       g.mbits = 0;
       for (int a = 0; a < 3; ++a) {
-        g.nc[a] = std::max(1, (int)std::floor(g.L[a] / (0.5 * rp)));
+        // cells are slices of the fractional coordinates; their width perpendicular to
+        // the faces is w_a / nc_a with w_a = 1 / |a*_a|, and a source within r_pair is
+        // at most ceil(r_pair / width) cells away along each axis
+        const double w = 1.0 / std::sqrt(g.Ar[a][0] * g.Ar[a][0] + g.Ar[a][1] * g.Ar[a][1] +
+                                         g.Ar[a][2] * g.Ar[a][2]);
+        g.nc[a] = std::max(1, (int)std::floor(w / (0.5 * rp)));
         g.nc[a] = std::min(g.nc[a], 64);
-        g.hc[a] = g.L[a] / g.nc[a];
+        g.hc[a] = w / g.nc[a];
         g.nr[a] = (int)std::ceil(rp / g.hc[a] - 1e-12);
+        for (int c = 0; c < 3; ++c) g.hv[a][c] = g.A[a][c] / g.nc[a];
         while ((1 << g.mbits) < g.nc[a]) ++g.mbits;
       }
       if (plan.prec == MBD_PREC_FP64) {

@@ -29,13 +29,17 @@ enum : uint32_t { kErrNotPosdef = 1u, kErrNonfinite = 2u, kErrNoConverge = 4u };
 // Everything one kernel launch needs to know about a system's geometry and grid.
 struct Geometry {
   int n;                 // atoms
-  double L[3];           // orthorhombic edges (bohr)
+  double L[3];           // cell vector lengths |a_a| (bohr)
+  double A[3][3];        // cell vectors a_a (rows, Cartesian bohr)
+  double Ar[3][3];       // reciprocal vectors a*_a (rows), a*_a . a_b = delta_ab
+  double Mu[3][3];       // K_a a*_a (rows): d u_a / d R, the B-spline chain-rule matrix
+  double hv[3][3];       // cell-list shift vectors a_a / nc_a (rows)
   int K[3];              // SPME grid
   int p;                 // spline order
   double tau;            // 1/bohr
   double r_pair;         // direct-space cutoff (bohr)
   int nc[3];             // cells per axis
-  double hc[3];          // cell edge per axis
+  double hc[3];          // cell-list cell width per axis, perpendicular to its faces
   int nr[3];             // neighbour-cell range per axis
   int mbits;             // bits per axis of the Morton cell index
   int tile[3];           // spread tile edge per axis (grid points)
@@ -80,15 +84,15 @@ struct SysBuffers {
   int* cell_start = nullptr;   // [cell_slots + 1], Morton-indexed
   int* cell_cursor = nullptr;  // [cell_slots]
   uint32_t* subkey = nullptr;  // [n] Morton code of the atom's sub-cell (order inside a cell)
-  double* wpos = nullptr;      // [n][3] wrapped positions, caller order
+  double* wpos = nullptr;      // [n][3] wrapped fractional coordinates in [0, 1), caller order
   void* loc = nullptr;         // Real [n][4] cell-local position + damping radius (sorted)
   double* g = nullptr;         // [n] omega sqrt(alpha) (sorted)
   double* om2 = nullptr;       // [n] omega^2 (sorted)
   int* base = nullptr;         // [n][3] spline base indices (sorted)
   int* scell = nullptr;        // [n] Morton cell index of each sorted atom
   void* th = nullptr;          // Real [n][3][p] M_p(w + t)
-  void* dth = nullptr;         // Real [n][3][p] (K_a / L_a) M_p'(w + t)
-  void* ddth = nullptr;        // Real [n][3][p] (K_a / L_a)^2 M_p''(w + t) (forces only)
+  void* dth = nullptr;         // Real [n][3][p] M_p'(w + t) (derivative in u_a)
+  void* ddth = nullptr;        // Real [n][3][p] M_p''(w + t) (forces only)
   int* tile_count = nullptr;   // [ntiles + 1]
   int* tile_start = nullptr;   // [ntiles + 1]
   int* tile_atoms = nullptr;   // [n * max tiles per stencil]

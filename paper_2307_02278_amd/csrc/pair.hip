@@ -2,11 +2,12 @@
 //   E_dir,i = sum over images n and atoms j with |R_j + n - R_i| < r_pair,
 //             except (j = i, n = 0), of T_dir(R_j + n - R_i) d_j,
 //   T_dir = T_erfc - (1 - f_ij) T = A(r) I - B(r) r r^T.
-// Cell list: atoms sorted by cell (edge >= r_pair / 2); the neighbour cells of a
-// cell are the offsets o in [-nr, nr]^3, wrapped periodically, and the
-// displacement is r = loc_j - loc_i + o * h with cell-local coordinates, so it
-// stays accurate in single precision and covers several images when r_pair
-// exceeds half the box.
+// Cell list: atoms sorted by cell (slices of the fractional coordinates, width
+// >= r_pair / 2 perpendicular to the faces); the neighbour cells of a cell are the
+// offsets o in [-nr, nr]^3, wrapped periodically, and the displacement is
+// r = loc_j - loc_i + sum_a o_a h_a with cell-local Cartesian coordinates and the
+// cell shift vectors h_a = a_a / nc_a, so it stays accurate in single precision,
+// works for any cell shape and covers several images when r_pair exceeds half the box.
 //
 // Two variants:
 //  - direct: one thread per target atom, all right-hand sides (B <= 8) in
@@ -46,15 +47,15 @@ k_pair_direct(const Geometry geo, const int* __restrict__ cell_start,
   for (int oz = -geo.nr[2]; oz <= geo.nr[2]; ++oz) {
     int wz = (cz + oz) % geo.nc[2];
     if (wz < 0) wz += geo.nc[2];
-    const R sz = (R)(oz * geo.hc[2]);
     for (int oy = -geo.nr[1]; oy <= geo.nr[1]; ++oy) {
       int wy = (cy + oy) % geo.nc[1];
       if (wy < 0) wy += geo.nc[1];
-      const R sy = (R)(oy * geo.hc[1]);
       for (int ox = -geo.nr[0]; ox <= geo.nr[0]; ++ox) {
         int wx = (cx + ox) % geo.nc[0];
         if (wx < 0) wx += geo.nc[0];
-        const R sx = (R)(ox * geo.hc[0]);
+        const R sx = (R)(ox * geo.hv[0][0] + oy * geo.hv[1][0] + oz * geo.hv[2][0]);
+        const R sy = (R)(ox * geo.hv[0][1] + oy * geo.hv[1][1] + oz * geo.hv[2][1]);
+        const R sz = (R)(ox * geo.hv[0][2] + oy * geo.hv[1][2] + oz * geo.hv[2][2]);
         const bool zero = (ox == 0 && oy == 0 && oz == 0);
         const int cc = cell_index(wx, wy, wz);
         const int j0 = cell_start[cc], j1 = cell_start[cc + 1];
@@ -117,7 +118,6 @@ k_pair_build(const Geometry geo, const int* __restrict__ cell_start,
   if (g0 >= geo.n) return;
   const int n = geo.n;
   const int nc0 = geo.nc[0], nc1 = geo.nc[1], nc2 = geo.nc[2];
-  const R h0 = (R)geo.hc[0], h1 = (R)geo.hc[1], h2 = (R)geo.hc[2];
   R(*tgt)[4] = tgt_all[wave];
   int(*tcell)[3] = tcell_all[wave];
 
@@ -129,7 +129,10 @@ k_pair_build(const Geometry geo, const int* __restrict__ cell_start,
   cell_coords(scell[tvalid ? ti : g0], tcx, tcy, tcz);
   const int dcx = tcx - c0x, dcy = tcy - c0y, dcz = tcz - c0z;
   const R* tl = loc + 4 * (size_t)(tvalid ? ti : g0);
-  const R tx = tl[0] + dcx * h0, ty = tl[1] + dcy * h1, tz = tl[2] + dcz * h2;
+  // target position relative to the corner of the group's first cell
+  const R tx = tl[0] + (R)(dcx * geo.hv[0][0] + dcy * geo.hv[1][0] + dcz * geo.hv[2][0]);
+  const R ty = tl[1] + (R)(dcx * geo.hv[0][1] + dcy * geo.hv[1][1] + dcz * geo.hv[2][1]);
+  const R tz = tl[2] + (R)(dcx * geo.hv[0][2] + dcy * geo.hv[1][2] + dcz * geo.hv[2][2]);
   if (lane < kGroup) {
     tgt[lane][0] = tx; tgt[lane][1] = ty; tgt[lane][2] = tz; tgt[lane][3] = tl[3];
     tcell[lane][0] = dcx; tcell[lane][1] = dcy; tcell[lane][2] = dcz;
@@ -162,7 +165,9 @@ k_pair_build(const Geometry geo, const int* __restrict__ cell_start,
         if (wx < 0) wx += nc0;
         const int cc = cell_index(wx, wy, wz);
         const int j0 = cell_start[cc], j1 = cell_start[cc + 1];
-        const R sx = dx * h0, sy = dy * h1, sz = dz * h2;
+        const R sx = (R)(dx * geo.hv[0][0] + dy * geo.hv[1][0] + dz * geo.hv[2][0]);
+        const R sy = (R)(dx * geo.hv[0][1] + dy * geo.hv[1][1] + dz * geo.hv[2][1]);
+        const R sz = (R)(dx * geo.hv[0][2] + dy * geo.hv[1][2] + dz * geo.hv[2][2]);
         for (int jb = j0; jb < j1; jb += 64) {
           const int j = jb + lane;
           uint32_t mask = 0;
@@ -463,9 +468,12 @@ __global__ void k_count_pairs(const Geometry geo, const int* __restrict__ cell_s
         const int cc = cell_index(wx, wy, wz);
         for (int j = cell_start[cc]; j < cell_start[cc + 1]; ++j) {
           if (zero && j == s) continue;
-          const R rx = loc[4 * j] - xi + (R)(ox * geo.hc[0]);
-          const R ry = loc[4 * j + 1] - yi + (R)(oy * geo.hc[1]);
-          const R rz = loc[4 * j + 2] - zi + (R)(oz * geo.hc[2]);
+          const R rx = loc[4 * j] - xi +
+                       (R)(ox * geo.hv[0][0] + oy * geo.hv[1][0] + oz * geo.hv[2][0]);
+          const R ry = loc[4 * j + 1] - yi +
+                       (R)(ox * geo.hv[0][1] + oy * geo.hv[1][1] + oz * geo.hv[2][1]);
+          const R rz = loc[4 * j + 2] - zi +
+                       (R)(ox * geo.hv[0][2] + oy * geo.hv[1][2] + oz * geo.hv[2][2]);
           cnt += (rx * rx + ry * ry + rz * rz < rp2) ? 1 : 0;
         }
       }

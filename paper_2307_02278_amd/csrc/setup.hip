@@ -1,8 +1,9 @@
-// Position-dependent setup (once per energy evaluation): wrap positions into the
-// cell, sort atoms by cell-list cell, cell-local coordinates for the pair kernel,
-// B-spline tables at the scaled fractional coordinates u_a = K_a R_a / L_a
-// (eq. scaledfractional, formed in double precision), and the per-tile atom lists
-// of the spread kernel.
+// Position-dependent setup (once per energy evaluation): fractional coordinates
+// a*_a . R wrapped into the cell, sort atoms by cell-list cell (cells are slices of
+// the fractional coordinates, so any right-handed cell works), cell-local Cartesian
+// coordinates for the pair kernel, B-spline tables at the scaled fractional
+// coordinates u_a = K_a a*_a . R (eq. scaledfractional, formed in double precision),
+// and the per-tile atom lists of the spread kernel.
 #include "common.h"
 #include "mbd_math.h"
 
@@ -10,26 +11,25 @@ namespace mbd {
 
 namespace {
 
-__global__ void k_wrap_count(int n, const double* __restrict__ pos, double L0, double L1,
-                             double L2, int nc0, int nc1, int nc2, double h0, double h1,
-                             double h2, double* __restrict__ wpos, int* __restrict__ cell_of,
+__global__ void k_wrap_count(const Geometry geo, const double* __restrict__ pos,
+                             double* __restrict__ wpos, int* __restrict__ cell_of,
                              uint32_t* __restrict__ subkey, int* __restrict__ count) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double L[3] = {L0, L1, L2};
-  const double h[3] = {h0, h1, h2};
-  const int nc[3] = {nc0, nc1, nc2};
+  if (i >= geo.n) return;
+  const double R0 = pos[3 * i], R1 = pos[3 * i + 1], R2 = pos[3 * i + 2];
   int c[3], f[3];
   for (int a = 0; a < 3; ++a) {
-    double x = pos[3 * i + a];
-    x -= L[a] * floor(x / L[a]);
-    if (x >= L[a]) x -= L[a];
+    // fractional coordinate a*_a . R, wrapped into [0, 1)
+    double x = geo.Ar[a][0] * R0 + geo.Ar[a][1] * R1 + geo.Ar[a][2] * R2;
+    x -= floor(x);
+    if (x >= 1.0) x -= 1.0;
     if (x < 0.0) x = 0.0;
     wpos[3 * i + a] = x;
-    int ci = (int)(x / h[a]);
-    c[a] = ci >= nc[a] ? nc[a] - 1 : ci;
+    const double xc = x * geo.nc[a];
+    int ci = (int)xc;
+    c[a] = ci >= geo.nc[a] ? geo.nc[a] - 1 : ci;
     // 4 sub-cells per axis order the atoms inside the cell
-    int fi = (int)((x - c[a] * h[a]) / h[a] * 4.0);
+    int fi = (int)((xc - c[a]) * 4.0);
     f[a] = fi < 0 ? 0 : (fi > 3 ? 3 : fi);
   }
   int cell = cell_index(c[0], c[1], c[2]);
@@ -108,17 +108,21 @@ __global__ void k_sorted_tables(Geometry geo, const int* __restrict__ perm,
   double x[3];
   int c[3];
   for (int a = 0; a < 3; ++a) {
-    x[a] = wpos[3 * i + a];
-    int ci = (int)(x[a] / geo.hc[a]);
+    x[a] = wpos[3 * i + a];  // fractional
+    int ci = (int)(x[a] * geo.nc[a]);
     c[a] = ci >= geo.nc[a] ? geo.nc[a] - 1 : ci;
   }
-  for (int a = 0; a < 3; ++a) loc[4 * s + a] = (R)(x[a] - c[a] * geo.hc[a]);
+  // cell-local Cartesian position: sum_a (x_a - c_a / nc_a) a_a
+  double rel[3];
+  for (int a = 0; a < 3; ++a) rel[a] = x[a] - (double)c[a] / geo.nc[a];
+  for (int q = 0; q < 3; ++q)
+    loc[4 * s + q] = (R)(rel[0] * geo.A[0][q] + rel[1] * geo.A[1][q] + rel[2] * geo.A[2][q]);
   scell[s] = cell_index(c[0], c[1], c[2]);
   loc[4 * s + 3] = (R)(geo.beta * rvdw[i]);
   g[s] = omega[i] * sqrt(alpha[i]);
   om2[s] = omega[i] * omega[i];
   for (int a = 0; a < 3; ++a) {
-    const double u = geo.K[a] * x[a] / geo.L[a];
+    const double u = geo.K[a] * x[a];
     double fl = floor(u);
     double w = u - fl;
     int b0 = (int)fl;
@@ -126,17 +130,17 @@ __global__ void k_sorted_tables(Geometry geo, const int* __restrict__ perm,
     b0 %= geo.K[a];
     if (b0 < 0) b0 += geo.K[a];
     base[3 * s + a] = b0;
+    // derivatives with respect to u_a; the kernels apply d u / d R = Mu
     double t[P], dt[P], ddt[P];
-    const double scale = geo.K[a] / geo.L[a];
     if (ddth) {
       bspline_weights2<P>(w, t, dt, ddt);
-      for (int k = 0; k < P; ++k) ddth[(s * 3 + a) * P + k] = (R)(ddt[k] * scale * scale);
+      for (int k = 0; k < P; ++k) ddth[(s * 3 + a) * P + k] = (R)ddt[k];
     } else {
       bspline_weights<P>(w, t, dt);
     }
     for (int k = 0; k < P; ++k) {
       th[(s * 3 + a) * P + k] = (R)t[k];
-      dth[(s * 3 + a) * P + k] = (R)(dt[k] * scale);
+      dth[(s * 3 + a) * P + k] = (R)dt[k];
     }
   }
   // tiles touched by the stencil k = base - t, t = 0..P-1 (mod K), per axis
@@ -223,9 +227,8 @@ void launch_setup(const Geometry& g, SysBuffers& b, const double* pos, const dou
   const int ncell = cell_slots(g);
   const int ntiles = g.tiles[0] * g.tiles[1] * g.tiles[2];
   fill_int(b.cell_cursor, 0, ncell, st);
-  k_wrap_count<<<blocks_for(g.n, 256), 256, 0, st>>>(
-      g.n, pos, g.L[0], g.L[1], g.L[2], g.nc[0], g.nc[1], g.nc[2], g.hc[0], g.hc[1], g.hc[2],
-      b.wpos, b.cell_of, b.subkey, b.cell_cursor);
+  k_wrap_count<<<blocks_for(g.n, 256), 256, 0, st>>>(g, pos, b.wpos, b.cell_of, b.subkey,
+                                                      b.cell_cursor);
   k_scan<<<1, 1024, 0, st>>>(ncell, b.cell_cursor, b.cell_start);
   fill_int(b.cell_cursor, 0, ncell, st);
   k_scatter<<<blocks_for(g.n, 256), 256, 0, st>>>(g.n, b.cell_of, b.cell_start, b.cell_cursor,

@@ -1,8 +1,10 @@
 // SPME spreading and gather (eqs. dipolarr and spme).
 //
 // Spread: D(k) = sum_j sum_a d_ja dW_j(k)/dR_a with W_j(k) = prod_a M_p(u_ja - k_a),
-// stencil k_a = base_a - t_a (t_a = 0..p-1, periodic wrap). The derivative table
-// dth already carries the K_a / L_a chain-rule factor (orthorhombic cells).
+// stencil k_a = base_a - t_a (t_a = 0..p-1, periodic wrap). With u = Mu R (Mu = rows
+// K_a a*_a, any cell), d . grad_R W = sum_b (Mu d)_b dW/du_b: the kernels transform the
+// dipole (spread), the gradient (gather) and the Hessian (force gather) with Mu and
+// use the derivative tables in u.
 // One wavefront owns a 4x4x4 tile of grid points for one chunk of BG right-hand
 // sides, accumulates in registers every atom whose stencil reaches the tile, in a
 // fixed order, and writes the tile once: no atomics, no clearing pass, and a
@@ -99,12 +101,18 @@ k_spread(const Geometry geo, const int* __restrict__ tile_start,
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const R m00 = (R)geo.Mu[0][0], m01 = (R)geo.Mu[0][1], m02 = (R)geo.Mu[0][2];
+    const R m10 = (R)geo.Mu[1][0], m11 = (R)geo.Mu[1][1], m12 = (R)geo.Mu[1][2];
+    const R m20 = (R)geo.Mu[2][0], m21 = (R)geo.Mu[2][1], m22 = (R)geo.Mu[2][2];
     int s = __builtin_amdgcn_readfirstlane(sat[0]);
     R n0 = dv[((size_t)s * 3 + 0) * B + bg];
     R n1 = dv[((size_t)s * 3 + 1) * B + bg];
     R n2 = dv[((size_t)s * 3 + 2) * B + bg];
     for (int a = 0; a < na; ++a) {
-      const R d0 = n0, d1 = n1, d2 = n2;
+      // dipole in u: (Mu d)_b
+      const R d0 = m00 * n0 + m01 * n1 + m02 * n2;
+      const R d1 = m10 * n0 + m11 * n1 + m12 * n2;
+      const R d2 = m20 * n0 + m21 * n1 + m22 * n2;
       if (a + 1 < na) {  // next atom's dipoles while this one is spread
         s = __builtin_amdgcn_readfirstlane(sat[a + 1]);
         n0 = dv[((size_t)s * 3 + 0) * B + bg];
@@ -240,6 +248,11 @@ k_gather_epilogue(const Geometry geo, const int* __restrict__ base, const R* __r
         e1 += __shfl_xor(e1, off);
         e2 += __shfl_xor(e2, off);
       }
+      // gradient in u -> Cartesian: E_c = sum_b Mu[b][c] (dE/du_b)
+      const R g0 = e0, g1 = e1, g2 = e2;
+      e0 = (R)geo.Mu[0][0] * g0 + (R)geo.Mu[1][0] * g1 + (R)geo.Mu[2][0] * g2;
+      e1 = (R)geo.Mu[0][1] * g0 + (R)geo.Mu[1][1] * g1 + (R)geo.Mu[2][1] * g2;
+      e2 = (R)geo.Mu[0][2] * g0 + (R)geo.Mu[1][2] * g1 + (R)geo.Mu[2][2] * g2;
     }
     if (sub == 0) {
       const double gs = g[s];
@@ -345,10 +358,17 @@ k_spme_force(const Geometry geo, const int* __restrict__ base, const R* __restri
       }
     }
     const size_t o = (size_t)s * 3 * B + bg;
-    const R h0 = hv[o], h1 = hv[o + B], h2 = hv[o + 2 * B];
-    double f0 = (double)(hxx * h0 + hxy * h1 + hxz * h2);
-    double f1 = (double)(hxy * h0 + hyy * h1 + hyz * h2);
-    double f2 = (double)(hxz * h0 + hyz * h1 + hzz * h2);
+    const R c0 = hv[o], c1 = hv[o + B], c2 = hv[o + 2 * B];
+    // Hessian in u: H_R = Mu^T H_u Mu, applied as Mu^T (H_u (Mu h))
+    const R h0 = (R)geo.Mu[0][0] * c0 + (R)geo.Mu[0][1] * c1 + (R)geo.Mu[0][2] * c2;
+    const R h1 = (R)geo.Mu[1][0] * c0 + (R)geo.Mu[1][1] * c1 + (R)geo.Mu[1][2] * c2;
+    const R h2 = (R)geo.Mu[2][0] * c0 + (R)geo.Mu[2][1] * c1 + (R)geo.Mu[2][2] * c2;
+    const R u0 = hxx * h0 + hxy * h1 + hxz * h2;
+    const R u1 = hxy * h0 + hyy * h1 + hyz * h2;
+    const R u2 = hxz * h0 + hyz * h1 + hzz * h2;
+    double f0 = (double)((R)geo.Mu[0][0] * u0 + (R)geo.Mu[1][0] * u1 + (R)geo.Mu[2][0] * u2);
+    double f1 = (double)((R)geo.Mu[0][1] * u0 + (R)geo.Mu[1][1] * u1 + (R)geo.Mu[2][1] * u2);
+    double f2 = (double)((R)geo.Mu[0][2] * u0 + (R)geo.Mu[1][2] * u1 + (R)geo.Mu[2][2] * u2);
     for (int off = 1; off < 64; off <<= 1) {
       f0 += __shfl_xor(f0, off);
       f1 += __shfl_xor(f1, off);

@@ -96,7 +96,7 @@ def _create(s, p, nsys=1):
     (lambda s, p: (setattr(p, "want_forces", 1), setattr(p, "block", 2)), L.MBD_E_ARG),
     (lambda s, p: setattr(s, "n_atoms", 0), L.MBD_E_ARG),
     (lambda s, p: setattr(s, "pos", None), L.MBD_E_ARG),
-    (lambda s, p: s.cell.__setitem__(1, 0.5), L.MBD_E_CELL),
+    (lambda s, p: [s.cell.__setitem__(3 + c, s.cell[c]) for c in range(3)], L.MBD_E_CELL),
     (lambda s, p: s.cell.__setitem__(0, -3.0), L.MBD_E_CELL),
     (lambda s, p: p.grid.__setitem__(0, 14), L.MBD_E_GRID),
     (lambda s, p: p.grid.__setitem__(1, 10), L.MBD_E_GRID),  # supported but < 2p
