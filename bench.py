@@ -24,6 +24,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -129,6 +131,69 @@ def energy_forces_leg(P, torch, synth, name, graph):
             "stage_ms": {k: round(v[0], 2) for k, v in stages.items() if v[1] > 0}}
 
 
+def probe_vector(P, seed, system, probe, n):
+    """Probe `probe` of `system` as the library defines it: sign of bit 63 of SplitMix64
+    output (probe 3N + 3i + a) of the stream seeded with output `system` of the stream
+    seeded with `seed`, scaled by 1/sqrt(3N) (computed with the library's host build)."""
+    from paper_2307_02278_amd import _lib
+    h = _lib.hostcheck()
+    zs = h.mbdh_splitmix(seed, system)
+    D = 3 * n
+    bits = np.array([h.mbdh_splitmix(zs, probe * D + k) >> 63 for k in range(D)], dtype=float)
+    return ((1.0 - 2.0 * bits) / math.sqrt(D)).reshape(n, 3)
+
+
+def delta11_study(P, torch, synth):
+    """Delta_11 = v^T C v for one fixed Rademacher probe (the first Lanczos diagonal),
+    by SPME-Ewald as a function of the grid and by the replica sum as a function of the
+    spherical cutoff, with the time of one evaluation (execute with m = 1). The replica
+    sum tends to the vacuum limit, which exceeds the tin-foil Ewald value by
+    (4 pi / 3V) |sum_i g_i v_i|^2; that corrected SPME value is reported beside it."""
+    A = synth.ANGSTROM_BOHR
+    out = {}
+    for name, s in (("water216", synth.water_box(216, seed=7)),
+                    ("diamond512", synth.diamond_box(4))):
+        ds = P.DeviceSystem(s.pos, s.cell, s.alpha, s.omega, s.rvdw)
+        V = float(abs(np.linalg.det(s.cell)))
+
+        def d11(**kw):
+            plan = P.Plan([ds], P.Params(n_probes=1, n_steps=1, block=1,
+                                         precision=P.PREC_FP64, seed=12345, **kw))
+            plan.execute()
+            torch.cuda.synchronize()
+            reps = 3
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                plan.execute()
+            torch.cuda.synchronize()
+            ms = 1000.0 * (time.perf_counter() - t0) / reps
+            plan.check()
+            a, _, _ = plan.tridiagonal()
+            plan.close()
+            return float(a[0, 0]), ms
+
+        spme = []
+        for K in (12, 16, 18, 20, 24, 30, 32, 36, 40, 48):
+            val, ms = d11(real_cutoff=7.0 * A, grid=(K, K, K))
+            spme.append([K, val, round(ms, 3)])
+        rep = []
+        for rc in (10.0, 15.0, 20.0, 30.0, 40.0, 60.0, 80.0, 100.0):
+            val, ms = d11(real_cutoff=7.0 * A, grid=(16, 16, 16), replica_cutoff=rc * A)
+            rep.append([rc, val, round(ms, 3)])
+        # surface term of the vacuum limit for this probe
+        g = s.omega * np.sqrt(s.alpha)
+        v = probe_vector(P, 12345, 0, 0, s.n)
+        surf = 4.0 * math.pi / (3.0 * V) * float(((g[:, None] * v).sum(0) ** 2).sum())
+        k18 = [r for r in spme if r[0] == 18][0]
+        out[name] = {"atoms": s.n, "box_angstrom": round(float(s.cell[0, 0]) / A, 3),
+                     "spme_vs_K": spme, "replica_vs_Rcut_angstrom": rep,
+                     "spme_plus_surface_at_K48": spme[-1][1] + surf,
+                     "cost_ratio_replica100A_over_spme_K18": round(rep[-1][2] / k18[2], 1)}
+        log(f"delta11 {name}: SPME K=48 {spme[-1][1]:.10f}, +surface {spme[-1][1] + surf:.10f}, "
+            f"replica 100 A {rep[-1][1]:.10f}; cost ratio {rep[-1][2] / k18[2]:.1f}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +210,9 @@ def main():
                     help="also time the uneven batch (32 water boxes, energy + forces)")
     ap.add_argument("--eager", action="store_true",
                     help="launch every kernel from the host instead of replaying HIP graphs")
+    ap.add_argument("--delta11", action="store_true",
+                    help="also run the Delta_11 convergence study (SPME vs grid, replica vs "
+                         "cutoff) on a 216-water box and a 512-atom diamond box")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -273,6 +341,8 @@ def main():
     # graph of that size did not keep (E+F 2.4 s replayed vs 2.1 s eager on one MI355X).
     uneven_leg = energy_forces_leg(P, torch, synth, "uneven", False) if args.uneven else None
 
+    d11 = delta11_study(P, torch, synth) if args.delta11 else None
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import method as om
@@ -322,6 +392,8 @@ def main():
     }
     if uneven_leg is not None:
         out["energy_forces_uneven"] = uneven_leg
+    if d11 is not None:
+        out["delta11"] = d11
     print(json.dumps(out), flush=True)
 
 

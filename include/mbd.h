@@ -98,6 +98,11 @@ typedef struct {
                            can return forces (needs block >= 4); 0 => energy only      */
   int32_t deterministic;/* reserved: every reduction already runs in a fixed order, so
                            results are bit-reproducible run to run on one device        */
+  double replica_cutoff;/* > 0 => replica method instead of Ewald/SPME (float64 only, no
+                           forces): T_ij = sum over images n with |R_j + n - R_i| <
+                           replica_cutoff of the damped tensor f T (eq. replica, spherical
+                           cutoff centred on atom i; tends to the vacuum boundary
+                           condition). 0 => SPME-Ewald                                 */
   int32_t graph;        /* 1 => mbd_execute records its whole launch sequence (all
                            systems, all streams) once into a HIP graph per variant
                            (energy / energy + forces) and replays it afterwards; the

@@ -46,6 +46,7 @@ class MbdParams(C.Structure):
         ("reorth", C.c_int32),
         ("want_forces", C.c_int32),
         ("deterministic", C.c_int32),
+        ("replica_cutoff", C.c_double),
         ("graph", C.c_int32),
     ]
 

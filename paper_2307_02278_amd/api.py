@@ -28,6 +28,7 @@ class Params:
     reorth: int = L.REORTH_NONE
     want_forces: bool = False
     graph: bool = False             # replay execute from a captured HIP graph
+    replica_cutoff: float = 0.0     # bohr; > 0 => replica method (float64, energy only)
 
     def to_c(self) -> L.MbdParams:
         p = L.MbdParams()
@@ -49,6 +50,7 @@ class Params:
         p.want_forces = 1 if self.want_forces else 0
         p.deterministic = 0
         p.graph = 1 if self.graph else 0
+        p.replica_cutoff = self.replica_cutoff
         return p
 
 

@@ -302,8 +302,14 @@ template <typename R>
 void matvec_block(Plan& plan, System& S, const double* w, uint32_t comps) {
   const hipStream_t st = plan.stream;
   const int nch = plan.B / plan.BG;
-  if (comps & MBD_C_DIR)
+  if (S.geo.replica_cut > 0.0) {
+    // replica method: Omega w + g (sum over images of f T) g w; no Ewald split
+    comps &= (MBD_C_DIAG | MBD_C_DIR);
+    if (comps & MBD_C_DIR)
+      staged(plan, MBD_STAGE_PAIR, [&] { launch_replica(S.geo, S.buf, plan.B, st); });
+  } else if (comps & MBD_C_DIR) {
     staged(plan, MBD_STAGE_PAIR, [&] { launch_pair<R>(S.geo, S.buf, plan.B, st); });
+  }
   for (int c = 0; c < nch; ++c) {
     if (comps & MBD_C_REC) {
       staged(plan, MBD_STAGE_SPREAD,
@@ -444,6 +450,14 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
   if (prm.want_forces && prm.block < 4)
     return fail(MBD_E_ARG, "forces need block >= 4");
   if (prm.graph != 0 && prm.graph != 1) return fail(MBD_E_ARG, "graph must be 0 or 1");
+  if (!std::isfinite(prm.replica_cutoff) || prm.replica_cutoff < 0.0)
+    return fail(MBD_E_ARG, "replica_cutoff must be finite and >= 0");
+  if (prm.replica_cutoff > 0.0) {
+    if (prm.precision != MBD_PREC_FP64)
+      return fail(MBD_E_ARG, "the replica method runs in float64 only");
+    if (prm.want_forces) return fail(MBD_E_ARG, "the replica method has no forces");
+    if (prm.block > 8) return fail(MBD_E_ARG, "the replica method needs block <= 8");
+  }
   for (int a = 0; a < 3; ++a)
     if (prm.grid[a] < 0) return fail(MBD_E_ARG, "grid sizes must be >= 0");
 
@@ -485,6 +499,8 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
                 : tau_from_cutoff_angstrom(prm.real_cutoff * kBohrAngstrom) * kBohrAngstrom;
     g.beta = prm.damp_beta;
     g.damp_d = prm.damp_d;
+    g.replica_cut = prm.replica_cutoff;
+    g.n_images = 0;
   }
 
   int ndev = 0;
@@ -551,6 +567,35 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
         g.nr[a] = (int)std::ceil(rp / g.hc[a] - 1e-12);
         for (int c = 0; c < 3; ++c) g.hv[a][c] = g.A[a][c] / g.nc[a];
         while ((1 << g.mbits) < g.nc[a]) ++g.mbits;
+      }
+      if (g.replica_cut > 0.0) {
+        // every lattice vector n with |n A| < R_cut + |a1| + |a2| + |a3| (any pair of
+        // atoms of the cell is closer than the sum of the cell vector lengths)
+        const double reach = g.replica_cut + g.L[0] + g.L[1] + g.L[2];
+        int nmax[3];
+        for (int a = 0; a < 3; ++a)
+          nmax[a] = 1 + (int)std::ceil(reach * std::sqrt(g.Ar[a][0] * g.Ar[a][0] +
+                                                         g.Ar[a][1] * g.Ar[a][1] +
+                                                         g.Ar[a][2] * g.Ar[a][2]));
+        std::vector<int> img;
+        for (int i = -nmax[0]; i <= nmax[0]; ++i)
+          for (int j = -nmax[1]; j <= nmax[1]; ++j)
+            for (int k = -nmax[2]; k <= nmax[2]; ++k) {
+              double v2 = 0.0;
+              for (int c = 0; c < 3; ++c) {
+                const double x = i * g.A[0][c] + j * g.A[1][c] + k * g.A[2][c];
+                v2 += x * x;
+              }
+              if (v2 < reach * reach) {
+                img.push_back(i);
+                img.push_back(j);
+                img.push_back(k);
+              }
+            }
+        g.n_images = (int)(img.size() / 3);
+        S.buf.images = dalloc<int>(plan, img.size(), S.bytes);
+        check(hipMemcpy(S.buf.images, img.data(), img.size() * sizeof(int),
+                        hipMemcpyHostToDevice), "copy images");
       }
       if (plan.prec == MBD_PREC_FP64) {
         allocate_system<double>(plan, S, prm.n_probes, prm.n_steps);

@@ -45,6 +45,8 @@ struct Geometry {
   int tile[3];           // spread tile edge per axis (grid points)
   int tiles[3];          // spread tiles per axis
   double beta, damp_d;
+  double replica_cut;    // > 0: replica method (damped tensor over images within this cutoff)
+  int n_images;          // replica image vectors
 };
 
 // Cells are numbered along a Morton (Z-order) curve so that consecutive sorted
@@ -98,6 +100,7 @@ struct SysBuffers {
   int* tile_atoms = nullptr;   // [n * max tiles per stencil]
   void* G = nullptr;           // Real [K3][K2][K1/2 + 1]
   void* tw = nullptr;          // Real [2][K1 + K2 + K3] twiddles exp(-2 pi i j / K_a)
+  int* images = nullptr;       // [n_images][3] integer lattice vectors (replica method)
   // direct-space tensor list (B >= 16): groups of kGroup sorted targets
   int pg_cap = 0;              // listed sources per group (capacity)
   int* pg_count = nullptr;     // [ngroups] listed sources (may exceed pg_cap: overflow)
@@ -185,6 +188,8 @@ void launch_setup(const Geometry& g, SysBuffers& b, const double* pos, const dou
 
 template <typename R>
 void launch_pair(const Geometry& g, const SysBuffers& b, int B, hipStream_t st);
+
+void launch_replica(const Geometry& g, const SysBuffers& b, int B, hipStream_t st);
 
 template <typename R>
 void launch_pair_build(const Geometry& g, const SysBuffers& b, bool count_only, hipStream_t st);

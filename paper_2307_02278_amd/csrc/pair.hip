@@ -446,6 +446,69 @@ k_pair_force(const Geometry geo, const int2* __restrict__ hdr, const R* __restri
   }
 }
 
+
+// Replica method (eq. replica): E_i = sum over images n and atoms j with
+// |R_j + n - R_i| < R_cut, except (j = i, n = 0), of f T(r) d_j, the damped bare tensor
+// (A = f / r^3, B = 3 f / r^5). Float64, any B <= 8 right-hand sides. One work-group
+// per target; its threads stride over the (image, source) pairs, and the partial
+// fields are reduced in LDS. Displacements are formed from fractional coordinates.
+template <int NB>
+__global__ void __launch_bounds__(256)
+k_replica(const Geometry geo, const int* __restrict__ perm, const double* __restrict__ frac,
+          const int* __restrict__ images, const double* __restrict__ loc,
+          const double* __restrict__ dv, double* __restrict__ Ed, int B) {
+  __shared__ double red[256];
+  const int s = blockIdx.x;
+  const int n = geo.n;
+  const int is = perm[s];
+  const double fi0 = frac[3 * is], fi1 = frac[3 * is + 1], fi2 = frac[3 * is + 2];
+  const double Si = loc[4 * s + 3];
+  const double rc2 = geo.replica_cut * geo.replica_cut;
+  double acc[NB][3];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b][0] = acc[b][1] = acc[b][2] = 0.0;
+  const long total = (long)geo.n_images * n;
+  for (long q = threadIdx.x; q < total; q += 256) {
+    const int im = (int)(q / n), j = (int)(q % n);
+    const int jo = perm[j];
+    const double u0 = frac[3 * jo] - fi0 + images[3 * im];
+    const double u1 = frac[3 * jo + 1] - fi1 + images[3 * im + 1];
+    const double u2 = frac[3 * jo + 2] - fi2 + images[3 * im + 2];
+    const double rx = u0 * geo.A[0][0] + u1 * geo.A[1][0] + u2 * geo.A[2][0];
+    const double ry = u0 * geo.A[0][1] + u1 * geo.A[1][1] + u2 * geo.A[2][1];
+    const double rz = u0 * geo.A[0][2] + u1 * geo.A[1][2] + u2 * geo.A[2][2];
+    const double r2 = rx * rx + ry * ry + rz * rz;
+    if (r2 >= rc2 || (j == s && r2 < 1e-12)) continue;
+    const double r = sqrt(r2);
+    const double ir2 = 1.0 / r2, ir3 = ir2 / r;
+    const double z = geo.damp_d * (r / (Si + loc[4 * j + 3]) - 1.0);
+    const double f = 1.0 / (1.0 + exp(-z));
+    const double A = f * ir3, Bk = 3.0 * f * ir3 * ir2;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      if (b >= B) break;
+      const double d0 = dv[(j * 3 + 0) * B + b];
+      const double d1 = dv[(j * 3 + 1) * B + b];
+      const double d2 = dv[(j * 3 + 2) * B + b];
+      const double rd = Bk * (rx * d0 + ry * d1 + rz * d2);
+      acc[b][0] += A * d0 - rx * rd;
+      acc[b][1] += A * d1 - ry * rd;
+      acc[b][2] += A * d2 - rz * rd;
+    }
+  }
+  for (int b = 0; b < NB && b < B; ++b)
+    for (int a = 0; a < 3; ++a) {
+      red[threadIdx.x] = acc[b][a];
+      __syncthreads();
+      for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) Ed[((size_t)s * 3 + a) * B + b] = red[0];
+      __syncthreads();
+    }
+}
+
 template <typename R>
 __global__ void k_count_pairs(const Geometry geo, const int* __restrict__ cell_start,
                               const int* __restrict__ scell, const R* __restrict__ loc,
@@ -601,6 +664,19 @@ void launch_pair_force(const Geometry& g, const SysBuffers& b, int B, hipStream_
 
 template void launch_pair_force<float>(const Geometry&, const SysBuffers&, int, hipStream_t);
 template void launch_pair_force<double>(const Geometry&, const SysBuffers&, int, hipStream_t);
+
+
+void launch_replica(const Geometry& g, const SysBuffers& b, int B, hipStream_t st) {
+  const double* loc = (const double*)b.loc;
+  const double* dv = (const double*)b.dv;
+  double* Ed = (double*)b.Ed;
+  switch (B) {
+    case 1: k_replica<1><<<g.n, 256, 0, st>>>(g, b.perm, b.wpos, b.images, loc, dv, Ed, B); break;
+    case 2: k_replica<2><<<g.n, 256, 0, st>>>(g, b.perm, b.wpos, b.images, loc, dv, Ed, B); break;
+    case 4: k_replica<4><<<g.n, 256, 0, st>>>(g, b.perm, b.wpos, b.images, loc, dv, Ed, B); break;
+    default: k_replica<8><<<g.n, 256, 0, st>>>(g, b.perm, b.wpos, b.images, loc, dv, Ed, B); break;
+  }
+}
 
 template void launch_pair<float>(const Geometry&, const SysBuffers&, int, hipStream_t);
 template void launch_pair<double>(const Geometry&, const SysBuffers&, int, hipStream_t);

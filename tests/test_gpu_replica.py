@@ -1,0 +1,85 @@
+"""Replica method on the GPU (eq. replica): the damped dipole tensor summed over all
+periodic images within a spherical cutoff centred on each atom, against the oracle's
+brute-force replica sum; and Delta_11 = v^T C v (the first Lanczos diagonal, the
+quantity of the paper's convergence study) through the full execute path."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import probes as opr
+from oracle import replica as orep
+
+pytestmark = pytest.mark.gpu
+
+A = synth.ANGSTROM_BOHR
+BETA, DAMP = 0.83, 6.0
+
+
+def _plan(s, rcut_ang, block=2, R=2, m=4):
+    import paper_2307_02278_amd as P
+    ds = P.DeviceSystem(s.pos, s.cell, s.alpha, s.omega, s.rvdw)
+    prm = P.Params(real_cutoff=9.0 * A, grid=(16, 16, 16), n_probes=R, n_steps=m, block=block,
+                   precision=P.PREC_FP64, replica_cutoff=rcut_ang * A, seed=12345)
+    return P.Plan([ds], prm)
+
+
+def _oracle_matvec(s, rcut_ang, v, comps):
+    """v (B, N, 3) -> (B, N, 3): Omega v (comps & 1) + g T_replica (g v) (comps & 2)."""
+    g = torch.as_tensor(s.omega * np.sqrt(s.alpha), dtype=torch.float64)
+    om2 = torch.as_tensor(s.omega ** 2, dtype=torch.float64)
+    vv = v.permute(1, 2, 0)
+    out = torch.zeros_like(vv)
+    if comps & 1:
+        out = out + om2[:, None, None] * vv
+    if comps & 2:
+        out = out + g[:, None, None] * orep.replica_field(s, BETA, DAMP, rcut_ang * A,
+                                                          g[:, None, None] * vv)
+    return out.permute(2, 0, 1)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return synth.workload("tiny").systems[0]
+
+
+@pytest.mark.parametrize("rcut,comps", [(12.0, 2), (25.0, 2), (25.0, 3)])
+def test_replica_matvec_matches_oracle(tiny, rcut, comps):
+    plan = _plan(tiny, rcut)
+    v = torch.randn(2, tiny.n, 3, dtype=torch.float64, generator=torch.Generator().manual_seed(4))
+    got = plan.matvec(v.cuda(), components=comps).cpu()
+    want = _oracle_matvec(tiny, rcut, v, comps)
+    assert float((got - want).norm() / want.norm()) < 1e-11
+
+
+def test_replica_matvec_triclinic_matches_oracle():
+    import importlib
+    tri = importlib.import_module("test_gpu_triclinic")._triclinic_system(n=40, seed=8)
+    plan = _plan(tri, 18.0)
+    v = torch.randn(2, tri.n, 3, dtype=torch.float64, generator=torch.Generator().manual_seed(6))
+    got = plan.matvec(v.cuda(), components=3).cpu()
+    want = _oracle_matvec(tri, 18.0, v, 3)
+    assert float((got - want).norm() / want.norm()) < 1e-11
+
+
+def test_delta11_through_execute(tiny):
+    """Delta_11 = a_1 of each probe's tridiagonal equals v^T C v with the shared probes."""
+    plan = _plan(tiny, 20.0, block=2, R=2, m=1)
+    plan.execute()
+    plan.check()
+    a, _, _ = plan.tridiagonal()
+    V = opr.rademacher(12345, 0, tiny.n, [0, 1])  # (2, N, 3) unit vectors
+    Cv = _oracle_matvec(tiny, 20.0, V, 3)
+    want = (V * Cv).sum(dim=(1, 2))
+    assert torch.allclose(a[:, 0], want, rtol=1e-11, atol=0)
+
+
+def test_replica_plan_rejects_mixed_precision_and_forces(tiny):
+    import paper_2307_02278_amd as P
+    ds = P.DeviceSystem(tiny.pos, tiny.cell, tiny.alpha, tiny.omega, tiny.rvdw)
+    for kw in (dict(precision=P.PREC_MIXED), dict(want_forces=True, block=4)):
+        prm = P.Params(grid=(16, 16, 16), n_probes=2, n_steps=2, replica_cutoff=20.0 * A,
+                       **{"block": 2, **kw})
+        with pytest.raises(P.MbdError) as ei:
+            P.Plan([ds], prm)
+        assert ei.value.code == -1
