@@ -21,4 +21,5 @@ Modules:
   lanczos  - Lanczos recurrence, Gauss quadrature and Hutchinson trace (Algorithms 1-2)
   dense    - exact energy from the full spectrum (eqs. plasmonic, plasmonic2)
   replica  - truncated replica sum over periodic images (eq. replica)
+  scs      - range-separated self-consistent screening of the polarizabilities (Review section)
 """
