@@ -61,7 +61,8 @@ enum {
   MBD_E_NODEVICE = -6,    /* no usable GPU                                                 */
   MBD_E_HIP = -7,         /* a HIP runtime call failed                                     */
   MBD_E_OOM = -8,         /* device allocation failed                                      */
-  MBD_E_STATE = -9        /* call out of order (e.g. tridiagonal requested before execute) */
+  MBD_E_STATE = -9,       /* call out of order (e.g. tridiagonal requested before execute) */
+  MBD_E_NOCONV = -10      /* an iterative solve stopped at its iteration limit             */
 };
 
 enum { MBD_PREC_FP64 = 0, MBD_PREC_MIXED = 1 /* FP32 SPME + pair kernel, FP64 Lanczos */ };
@@ -180,6 +181,53 @@ mbd_status mbd_get_tridiagonal(mbd_plan plan, int32_t sys, double* a, double* b,
 /* Per-probe quadrature values Q_l = sum_k U_1k^2 sqrt(theta_k) of the last execute
  * (synchronizes). q: host [R]. */
 mbd_status mbd_get_quadrature(mbd_plan plan, int32_t sys, double* q);
+
+/* ---- Self-consistent screening (range-separated SCS of MBD@rsSCS) -------------------
+ *
+ * The Review section names the step upstream of the MBD matrix: the polarizabilities are
+ * made frequency dependent and screened by a Dyson-like equation solved at a set of
+ * imaginary frequencies; the paper does not write it out. Solved here, for one system of a
+ * plan at its current positions, with
+ *   alpha_i(iu) = alpha_i / (1 + (u / omega_i)^2)                   (one-oscillator model)
+ *   (A(iu)^-1 + T_SR(iu)) X_k = E_k,  E_k = unit vector k on every atom, k = 1..3
+ *   alpha^SCS_i(iu) = (1/3) sum_k (X_k)_{i,k}     (= (1/3) tr sum_j [(A^-1 + T_SR)^-1]_ij)
+ *   T_SR = (1 - f) T_GG,  T_GG = -grad grad (erf(r / sigma_ij) / r),
+ *   sigma_ij^2 = sigma_i^2 + sigma_j^2,  sigma_i = (sqrt(2/pi) alpha_i(iu) / 3)^(1/3),
+ * f the Fermi damping of the plan (beta, d, the system's unscreened r_vdw), summed over
+ * every periodic image within the plan's pair cutoff (mbd_info.r_pair; 1 - f makes T_SR
+ * short-ranged, so no Ewald split is involved). Then, with the Casimir-Polder integral on
+ * an n-point Gauss-Legendre grid mapped by u = L (1 + x) / (1 - x),
+ *   C6_i = (3/pi) sum_q w_q alpha^SCS_i(iu_q)^2,   omega^SCS_i = 4 C6_i / (3 alpha^SCS_i(0)^2),
+ *   r_vdw^SCS_i = r_vdw_i (alpha^SCS_i(0) / alpha_i)^(1/3).
+ * The 3 (n + 1) right-hand sides (static point plus n nodes) run together through a
+ * Jacobi-preconditioned conjugate gradient in float64 on the device, whatever the plan's
+ * precision. */
+typedef struct {
+  int32_t n_freq;       /* quadrature nodes n, 1..31; 0 => 15                              */
+  double freq_scale;    /* L of the frequency map, Hartree; <= 0 => 0.6                    */
+  double tol;           /* stop when ||r|| <= tol ||E_k|| for every right-hand side;
+                           <= 0 => 1e-10                                                    */
+  int32_t max_iter;     /* conjugate-gradient iteration limit; <= 0 => 1000                */
+} mbd_scs_params;
+
+typedef struct {
+  int32_t iterations;       /* conjugate-gradient iterations run                           */
+  double max_rel_residual;  /* max over right-hand sides of ||r|| / ||E_k|| at exit        */
+} mbd_scs_info;
+
+/* Screened alpha(0), omega and r_vdw of system `sys`, in the caller's atom order:
+ * alpha_scs, omega_scs, rvdw_scs: device [N] float64 (required);
+ * alpha_freq: device [n][N] float64 alpha^SCS at the quadrature nodes u_q (ascending), or NULL;
+ * info: host, or NULL.
+ * Synchronous: runs on the plan's stream, allocates a per-call device workspace of
+ * 5 x 3 (n + 1) x 3N doubles plus small tables, and frees it before returning. The
+ * outputs feed a new plan (MBD@rsSCS): mbd_plan_create with alpha_scs, omega_scs and
+ * rvdw_scs as the system's parameters. Errors: MBD_E_ARG (bad arguments),
+ * MBD_E_NOT_POSDEF (p^T M p <= 0: the screening matrix is not positive definite at some
+ * frequency), MBD_E_NOCONV (max_iter reached; outputs are written from the last iterate),
+ * MBD_E_HIP, MBD_E_OOM. */
+mbd_status mbd_scs(mbd_plan plan, int32_t sys, const mbd_scs_params* prm, double* alpha_scs,
+                   double* omega_scs, double* rvdw_scs, double* alpha_freq, mbd_scs_info* info);
 
 mbd_status mbd_plan_destroy(mbd_plan plan);
 

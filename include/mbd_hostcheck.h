@@ -47,6 +47,10 @@ void mbdh_direct_kernel_grad(double r2, double tau, double inv_s, double damp_d,
 int32_t mbdh_tridiag_adjoint(const double* a, const double* b, int32_t n, double* abar,
                              double* bbar);
 
+/* Gauss-Legendre nodes x[0..n-1] (ascending) and weights w[0..n-1] on [-1, 1], n >= 1: the
+ * rule behind the imaginary-frequency grid of mbd_scs. */
+void mbdh_gauss_legendre(int32_t n, double* x, double* w);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,7 +5,8 @@ this package does not load it; the first call into the binding does, and it
 raises ImportError when the library is not built. There is no CPU fallback.
 """
 from ._lib import (  # noqa: F401
-    C_ALL, C_DIAG, C_DIR, C_REC, C_SELF, PREC_FP64, PREC_MIXED, REORTH_FULL, REORTH_LOCAL,
-    REORTH_NONE, MbdError,
+    C_ALL, C_DIAG, C_DIR, C_REC, C_SELF, MBD_E_ARG, MBD_E_CELL, MBD_E_GRID, MBD_E_HIP,
+    MBD_E_NOCONV, MBD_E_NODEVICE, MBD_E_NONFINITE, MBD_E_NOT_POSDEF, MBD_E_OOM, MBD_E_STATE,
+    MBD_OK, PREC_FP64, PREC_MIXED, REORTH_FULL, REORTH_LOCAL, REORTH_NONE, MbdError,
 )
 from .api import DeviceSystem, MBDEnergy, Params, Plan, energy  # noqa: F401

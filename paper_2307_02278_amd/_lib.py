@@ -10,7 +10,7 @@ HOSTCHECK_PATH = os.path.join(HERE, "libmbd_hostcheck.so")
 
 MBD_OK = 0
 MBD_E_ARG, MBD_E_CELL, MBD_E_GRID, MBD_E_NOT_POSDEF, MBD_E_NONFINITE = -1, -2, -3, -4, -5
-MBD_E_NODEVICE, MBD_E_HIP, MBD_E_OOM, MBD_E_STATE = -6, -7, -8, -9
+MBD_E_NODEVICE, MBD_E_HIP, MBD_E_OOM, MBD_E_STATE, MBD_E_NOCONV = -6, -7, -8, -9, -10
 PREC_FP64, PREC_MIXED = 0, 1
 REORTH_NONE, REORTH_LOCAL, REORTH_FULL = 0, 1, 2
 C_DIAG, C_DIR, C_REC, C_SELF, C_ALL = 1, 2, 4, 8, 15
@@ -64,6 +64,22 @@ class MbdInfo(C.Structure):
     ]
 
 
+class MbdScsParams(C.Structure):
+    _fields_ = [
+        ("n_freq", C.c_int32),
+        ("freq_scale", C.c_double),
+        ("tol", C.c_double),
+        ("max_iter", C.c_int32),
+    ]
+
+
+class MbdScsInfo(C.Structure):
+    _fields_ = [
+        ("iterations", C.c_int32),
+        ("max_rel_residual", C.c_double),
+    ]
+
+
 # (name, restype, argtypes) for every entry point declared in include/mbd.h
 SIGNATURES = [
     ("mbd_plan_create", C.c_int32,
@@ -83,6 +99,9 @@ SIGNATURES = [
     ("mbd_set_timing", C.c_int32, [C.c_void_p, C.c_int32]),
     ("mbd_get_stage_times", C.c_int32,
      [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    ("mbd_scs", C.c_int32,
+     [C.c_void_p, C.c_int32, C.POINTER(MbdScsParams), C.c_void_p, C.c_void_p, C.c_void_p,
+      C.c_void_p, C.POINTER(MbdScsInfo)]),
     ("mbd_status_string", C.c_char_p, [C.c_int32]),
     ("mbd_last_error", C.c_char_p, []),
 ]
@@ -104,6 +123,7 @@ HOSTCHECK_SIGNATURES = [
     ("mbdh_tridiag_adjoint", C.c_int32,
      [C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
       C.POINTER(C.c_double)]),
+    ("mbdh_gauss_legendre", None, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
 ]
 
 _lib = None

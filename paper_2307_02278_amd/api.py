@@ -157,6 +157,25 @@ class Plan:
         L.check(self.lib.mbd_get_stage_times(self.handle, ms, cnt))
         return {L.STAGES[i]: (ms[i], cnt[i]) for i in range(n)}
 
+    def scs(self, sys: int = 0, n_freq: int = 15, freq_scale: float = 0.6, tol: float = 1e-10,
+            max_iter: int = 1000, with_freq: bool = False):
+        """Range-separated self-consistent screening of system `sys` at its current
+        positions (mbd_scs). Returns (alpha, omega, r_vdw) screened, float64 on the GPU in
+        the caller's atom order, plus alpha^SCS at the n_freq quadrature nodes [n_freq, N]
+        when with_freq, and an info dict (iterations, max_rel_residual)."""
+        n = self.systems[sys].n
+        out = torch.empty(3, n, dtype=torch.float64, device="cuda")
+        af = torch.empty(n_freq, n, dtype=torch.float64, device="cuda") if with_freq else None
+        prm = L.MbdScsParams(n_freq, freq_scale, tol, max_iter)
+        inf = L.MbdScsInfo()
+        L.check(self.lib.mbd_scs(self.handle, sys, C.byref(prm), C.c_void_p(out[0].data_ptr()),
+                                 C.c_void_p(out[1].data_ptr()), C.c_void_p(out[2].data_ptr()),
+                                 C.c_void_p(af.data_ptr()) if with_freq else None,
+                                 C.byref(inf)))
+        info = {"iterations": inf.iterations, "max_rel_residual": inf.max_rel_residual}
+        res = (out[0], out[1], out[2])
+        return res + ((af,) if with_freq else ()) + (info,)
+
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             self.lib.mbd_plan_destroy(self.handle)

@@ -405,6 +405,7 @@ const char* mbd_status_string(mbd_status s) {
     case MBD_E_HIP: return "HIP runtime error";
     case MBD_E_OOM: return "out of device memory";
     case MBD_E_STATE: return "call out of order";
+    case MBD_E_NOCONV: return "iterative solve did not converge";
     default: return "unknown status";
   }
 }
@@ -880,6 +881,113 @@ mbd_status mbd_get_quadrature(mbd_plan plan, int32_t sys, double* q) {
       hipMemcpy(q, P.sys[sys].buf.q, sizeof(double) * P.prm.n_probes, hipMemcpyDeviceToHost) !=
           hipSuccess)
     return fail(MBD_E_HIP, "copy failed");
+  return MBD_OK;
+}
+
+mbd_status mbd_scs(mbd_plan plan, int32_t sys, const mbd_scs_params* prm_in, double* alpha_scs,
+                   double* omega_scs, double* rvdw_scs, double* alpha_freq, mbd_scs_info* info) {
+  using namespace mbd;
+  if (!plan || !prm_in || !alpha_scs || !omega_scs || !rvdw_scs)
+    return fail(MBD_E_ARG, "NULL argument");
+  Plan& P = plan->plan;
+  if (sys < 0 || sys >= (int)P.sys.size()) return fail(MBD_E_ARG, "system index out of range");
+  mbd_scs_params prm = *prm_in;
+  if (prm.n_freq == 0) prm.n_freq = 15;
+  if (prm.n_freq < 1 || prm.n_freq > 31) return fail(MBD_E_ARG, "n_freq must be in [1, 31]");
+  if (!std::isfinite(prm.freq_scale) || !std::isfinite(prm.tol))
+    return fail(MBD_E_ARG, "freq_scale and tol must be finite");
+  if (prm.freq_scale <= 0.0) prm.freq_scale = 0.6;
+  if (prm.tol <= 0.0) prm.tol = 1e-10;
+  if (prm.max_iter <= 0) prm.max_iter = 1000;
+  System& S = P.sys[sys];
+  const hipStream_t st = P.stream;
+  ScsWork w;
+  w.n = S.geo.n;
+  w.nq = prm.n_freq + 1;  // the static point u = 0, then the quadrature nodes
+  w.ncol = 3 * w.nq;
+  w.nblk = std::max(1, std::min(512, (3 * w.n + 127) / 128));
+  // node 0: u = 0 (no weight); nodes 1..n: u = L (1 + x) / (1 - x), w = 2 L w_x / (1 - x)^2
+  std::vector<double> x(prm.n_freq), wx(prm.n_freq), u(w.nq, 0.0), wq(w.nq, 0.0);
+  gauss_legendre(prm.n_freq, x.data(), wx.data());
+  for (int q = 0; q < prm.n_freq; ++q) {
+    u[q + 1] = prm.freq_scale * (1.0 + x[q]) / (1.0 - x[q]);
+    wq[q + 1] = wx[q] * 2.0 * prm.freq_scale / ((1.0 - x[q]) * (1.0 - x[q]));
+  }
+  std::vector<void*> mem;
+  auto alloc = [&](size_t count) {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(double)) != hipSuccess)
+      throw std::bad_alloc();
+    mem.push_back(p);
+    return static_cast<double*>(p);
+  };
+  auto release = [&] {
+    for (void* p : mem) hipFree(p);
+    mem.clear();
+  };
+  int iters = 0, nact = 0;
+  uint32_t stat = 0;
+  std::vector<double> sc;
+  try {
+    const size_t vec = (size_t)w.n * 3 * w.ncol;
+    w.locd = alloc(4 * (size_t)w.n);
+    w.ainv = alloc((size_t)w.n * w.nq);
+    w.sig2 = alloc((size_t)w.n * w.nq);
+    w.x = alloc(vec);
+    w.r = alloc(vec);
+    w.z = alloc(vec);
+    w.p = alloc(vec);
+    w.q = alloc(vec);
+    w.part = alloc((size_t)w.nblk * 2 * w.ncol);
+    w.sc = alloc(8 * (size_t)w.ncol);
+    w.nact = reinterpret_cast<int*>(alloc(1));
+    double* u_d = alloc(w.nq);
+    double* w_d = alloc(w.nq);
+    check(hipStreamSynchronize(st), "scs");
+    check(hipMemcpy(u_d, u.data(), sizeof(double) * w.nq, hipMemcpyHostToDevice), "scs nodes");
+    check(hipMemcpy(w_d, wq.data(), sizeof(double) * w.nq, hipMemcpyHostToDevice), "scs nodes");
+    fill_int(reinterpret_cast<int*>(P.status), 0, 1, st);
+    launch_scs_prepare(S.geo, S.buf, S.src.alpha, S.src.omega, S.src.r_vdw, u_d, w, st);
+    launch_scs_init(w, st);
+    nact = w.ncol;
+    while (nact > 0 && iters < prm.max_iter) {
+      launch_scs_iteration(S.geo, S.buf, w, prm.tol, P.status, st);
+      ++iters;
+      check(hipGetLastError(), "scs iteration");
+      check(hipMemcpyAsync(&nact, w.nact, sizeof(int), hipMemcpyDeviceToHost, st), "scs");
+      check(hipStreamSynchronize(st), "scs");
+    }
+    launch_scs_output(S.buf, w, w_d, S.src.alpha, S.src.r_vdw, alpha_scs, omega_scs, rvdw_scs,
+                      alpha_freq, st);
+    check(hipGetLastError(), "scs output");
+    sc.resize(8 * (size_t)w.ncol);
+    check(hipMemcpyAsync(sc.data(), w.sc, sizeof(double) * sc.size(), hipMemcpyDeviceToHost, st),
+          "scs");
+    check(hipMemcpyAsync(&stat, P.status, sizeof(stat), hipMemcpyDeviceToHost, st), "scs");
+    check(hipStreamSynchronize(st), "scs");
+  } catch (const std::bad_alloc&) {
+    hipStreamSynchronize(st);
+    release();
+    return fail(MBD_E_OOM, "device allocation failed (scs workspace)");
+  } catch (const HipError& e) {
+    hipStreamSynchronize(st);
+    release();
+    return fail(MBD_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
+  release();
+  if (info) {
+    // sc rows 4 (||r||^2) and 6 (||E_k||^2)
+    double worst = 0.0;
+    for (int c = 0; c < w.ncol; ++c)
+      worst = std::max(worst, std::sqrt(sc[4 * w.ncol + c] / sc[6 * w.ncol + c]));
+    info->iterations = iters;
+    info->max_rel_residual = worst;
+  }
+  if (stat & kErrNotPosdef)
+    return fail(MBD_E_NOT_POSDEF, "screening matrix not positive definite (p^T M p <= 0)");
+  if (nact > 0)
+    return fail(MBD_E_NOCONV, "screening solve reached max_iter = " +
+                                  std::to_string(prm.max_iter));
   return MBD_OK;
 }
 

@@ -247,6 +247,29 @@ void launch_forces_finish(const Geometry& g, const SysBuffers& b, int R, double*
                           hipStream_t st);
 void fill_double(double* p, double v, size_t n, hipStream_t st);
 
+// self-consistent screening (conjugate gradient over 3 nq right-hand sides)
+struct ScsWork {
+  int n = 0, nq = 0, ncol = 0, nblk = 0;
+  double* locd = nullptr;   // [n][4] sorted cell-local position (float64) and beta R_vdW
+  double* ainv = nullptr;   // [n][nq] 1 / alpha_i(iu_q)
+  double* sig2 = nullptr;   // [n][nq] sigma_i(u_q)^2
+  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;  // [n][3][ncol]
+  double* part = nullptr;   // [nblk][2][ncol] partial dot products
+  double* sc = nullptr;     // [8][ncol] CG scalars
+  int* nact = nullptr;      // [1] columns still iterating
+};
+void launch_scs_prepare(const Geometry& g, const SysBuffers& b, const double* alpha,
+                        const double* omega, const double* rvdw, const double* u,
+                        const ScsWork& w, hipStream_t st);
+void launch_scs_apply(const Geometry& g, const SysBuffers& b, const ScsWork& w, const double* p,
+                      double* q, hipStream_t st);
+void launch_scs_init(const ScsWork& w, hipStream_t st);
+void launch_scs_iteration(const Geometry& g, const SysBuffers& b, const ScsWork& w, double tol,
+                          uint32_t* status, hipStream_t st);
+void launch_scs_output(const SysBuffers& b, const ScsWork& w, const double* wq,
+                       const double* alpha, const double* rvdw, double* a_out, double* om_out,
+                       double* rv_out, double* af_out, hipStream_t st);
+
 bool fft_supported(int k);
 void set_error(const std::string& msg);
 

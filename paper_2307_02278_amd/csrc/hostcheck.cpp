@@ -62,4 +62,6 @@ int32_t mbdh_tridiag_adjoint(const double* a, const double* b, int32_t n, double
   return 1;
 }
 
+void mbdh_gauss_legendre(int32_t n, double* x, double* w) { mbd::gauss_legendre(n, x, w); }
+
 }  // extern "C"

@@ -326,4 +326,30 @@ MBD_HD void tridiag_sqrt_adjoint(const double* theta, const double* u, int n, in
   }
 }
 
+// Gauss-Legendre rule on [-1, 1]: the nodes are the roots of the Legendre polynomial
+// P_n, found by Newton's method from the asymptotic guesses cos(pi (i + 3/4) / (n + 1/2));
+// P_n and P_n' come from the three-term recurrence (j + 1) P_{j+1} = (2j + 1) x P_j - j P_{j-1}
+// and P_n'(x) = n (x P_n - P_{n-1}) / (x^2 - 1); the weights are 2 / ((1 - x^2) P_n'(x)^2).
+// Nodes are returned in ascending order.
+inline void gauss_legendre(int n, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double z = cos(3.14159265358979323846 * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = 0.0;
+      for (int j = 1; j <= n; ++j) {
+        const double pm = p1;
+        p1 = p0;
+        p0 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * pm) / j;
+      }
+      dp = n * (z * p0 - p1) / (z * z - 1.0);
+      const double dz = p0 / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-16) break;
+    }
+    x[i] = -z;  // the guesses descend from 1; their negatives ascend (the rule is symmetric)
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
 }  // namespace mbd

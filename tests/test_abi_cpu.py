@@ -124,6 +124,20 @@ def test_null_handles_are_rejected():
     assert lib.mbd_execute(None, None, None) == L.MBD_E_ARG
     assert lib.mbd_matvec(None, 0, None, None, 1, 15) == L.MBD_E_ARG
     assert lib.mbd_plan_destroy(None) == L.MBD_OK
+    prm = L.MbdScsParams(15, 0.6, 1e-10, 100)
+    assert lib.mbd_scs(None, 0, C.byref(prm), None, None, None, None, None) == L.MBD_E_ARG
+    assert lib.mbd_status_string(L.MBD_E_NOCONV) == b"iterative solve did not converge"
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 15, 31])
+def test_hostcheck_gauss_legendre_matches_numpy(n):
+    h = L.hostcheck()
+    x, w = (C.c_double * n)(), (C.c_double * n)()
+    h.mbdh_gauss_legendre(n, x, w)
+    xr, wr = np.polynomial.legendre.leggauss(n)
+    assert np.allclose(np.array(x[:]), xr, rtol=0, atol=1e-15)
+    assert np.allclose(np.array(w[:]), wr, rtol=1e-12, atol=0)
+    assert abs(sum(w[:]) - 2.0) < 1e-14
 
 
 # --- kernel scalar math on the host vs the oracle ---------------------------------
