@@ -194,6 +194,27 @@ def delta11_study(P, torch, synth):
     return out
 
 
+def scs_timing(plan, torch, s, n_pairs, n_freq=15):
+    """Range-separated SCS of the 24k water box at its current positions (static point +
+    n_freq nodes, 3 (n_freq + 1) right-hand sides in one float64 conjugate gradient):
+    wall time of one call after a warm-up call, iterations, and the rate of
+    (pair, frequency) tensor evaluations of the operator kernel."""
+    plan.scs(n_freq=n_freq)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a, o, r, info = plan.scs(n_freq=n_freq)
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0)
+    ratio = a.cpu().numpy() / s.alpha
+    it = info["iterations"]
+    log(f"scs: {ms:.1f} ms, {it} iterations, residual {info['max_rel_residual']:.2e}")
+    return {"workload": "water box N=24000 (the headline box)", "n_freq": n_freq,
+            "ms": round(ms, 2), "iterations": it, "ms_per_iteration": round(ms / max(it, 1), 3),
+            "max_rel_residual": info["max_rel_residual"],
+            "pair_frequency_evals_per_s": round(n_pairs * (n_freq + 1) * it / (ms * 1e-3), 1),
+            "alpha_scs_over_alpha": [round(float(ratio.min()), 4), round(float(ratio.max()), 4)]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,6 +231,8 @@ def main():
                     help="also time the uneven batch (32 water boxes, energy + forces)")
     ap.add_argument("--eager", action="store_true",
                     help="launch every kernel from the host instead of replaying HIP graphs")
+    ap.add_argument("--no-scs", action="store_true",
+                    help="skip the self-consistent screening leg on the 24k box")
     ap.add_argument("--delta11", action="store_true",
                     help="also run the Delta_11 convergence study (SPME vs grid, replica vs "
                          "cutoff) on a 216-water box and a 512-atom diamond box")
@@ -314,6 +337,7 @@ def main():
     # Whole-matvec algorithmic bytes 24 K^3 + 48 N per probe-vector.
     bmv = 24.0 * K[0] * K[1] * K[2] + 48.0 * s.n
     path_gbs = bmv * value / 1e9
+    scs_leg = None if args.no_scs else scs_timing(plan, torch, s, n_pairs)
     plan.close()
 
     # Plain form: one probe vector at a time in float64, same kernels, same GPU.
@@ -389,6 +413,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "energy_forces": forces_leg,
+        "scs": scs_leg,
     }
     if uneven_leg is not None:
         out["energy_forces_uneven"] = uneven_leg
