@@ -367,16 +367,21 @@ __device__ __forceinline__ void pair_dif(float (&xr)[K / 2], float (&xi)[K / 2],
     // lane 0 holds x[k], lane 1 holds x[k + H]
     const float ar = h ? pr : xr[k], ai = h ? pi : xi[k];
     const float br = h ? xr[k] : pr, bi = h ? xi[k] : pi;
-    if (h == 0) {
-      xr[k] = ar + br;
-      xi[k] = ai + bi;
-    } else {
-      const float dr = ar - br, di = ai - bi;
-      const float wc = T.c[k], ws = FWD ? -T.s[k] : T.s[k];
-      xr[k] = dr * wc - di * ws;
-      xi[k] = dr * ws + di * wc;
-    }
+    // both halves computed, one selected: no divergent branch per element
+    const float dr = ar - br, di = ai - bi;
+    const float wc = T.c[k], ws = FWD ? -T.s[k] : T.s[k];
+    const float tr = dr * wc - di * ws, ti = dr * ws + di * wc;
+    xr[k] = h ? tr : ar + br;
+    xi[k] = h ? ti : ai + bi;
   }
+}
+
+// Element e of a grid line, addressed from a wave-uniform base by a 32-bit byte offset,
+// so that every load and store is one scalar base plus a 32-bit per-lane offset (no
+// per-element 64-bit address kept live). Offsets stay below 2^32 bytes: one grid chunk
+// is at most 128 x 128 x 130 x 64 floats.
+__device__ __forceinline__ float& at(float* base, uint32_t e) {
+  return *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + (e << 2));
 }
 
 template <int K, int MODE>
@@ -420,7 +425,7 @@ k_fft_reg(float* __restrict__ grid, GridDims gd, const float* __restrict__ G) {
   if (MODE == kXFwd) {
 #pragma unroll
     for (int m = 0; m < H; ++m) {
-      xr[m] = gw[lo + (uint32_t)(2 * m + h) * stride];
+      xr[m] = at(gw, lo + (uint32_t)(2 * m + h) * stride);
       xi[m] = 0.f;
     }
   } else if (MODE == kXInv) {
@@ -428,8 +433,8 @@ k_fft_reg(float* __restrict__ grid, GridDims gd, const float* __restrict__ G) {
     for (int m = 0; m < H; ++m) {
       const int n = 2 * m + h;
       const int kk = n <= H ? n : K - n;
-      const float vr = gw[lo + (uint32_t)(2 * kk) * stride];
-      const float vi = gw[lo + (uint32_t)(2 * kk + 1) * stride];
+      const float vr = at(gw, lo + (uint32_t)(2 * kk) * stride);
+      const float vi = at(gw, lo + (uint32_t)(2 * kk + 1) * stride);
       xr[m] = vr;
       xi[m] = n <= H ? vi : -vi;
     }
@@ -437,8 +442,8 @@ k_fft_reg(float* __restrict__ grid, GridDims gd, const float* __restrict__ G) {
 #pragma unroll
     for (int m = 0; m < H; ++m) {
       const uint32_t o = lo + (uint32_t)(2 * m + h) * stride;
-      xr[m] = gw[o];
-      xi[m] = gw[o + BG];
+      xr[m] = at(gw, o);
+      xi[m] = at(gw, o + BG);
     }
   }
   constexpr bool FWD = (MODE == kXFwd || MODE == kYFwd || MODE == kZConv);
@@ -446,12 +451,12 @@ k_fft_reg(float* __restrict__ grid, GridDims gd, const float* __restrict__ G) {
   pair_dit<K, FWD>(xr, xi, h);
   if (MODE == kZConv) {
     // natural halves: lane h holds X[h H + k]
-    const long y = line / gd.KX, kx = line % gd.KX;
-    const float* Gl = G + (size_t)y * gd.KX + kx;
+    // G is [K3][K2][KX]: a 32-bit offset from the kernel-argument base per element
+    const uint32_t goff = (uint32_t)line;  // y * KX + kx
     const uint32_t gstride = (uint32_t)gd.K2 * gd.KX;
 #pragma unroll
     for (int k = 0; k < H; ++k) {
-      const float w = Gl[(uint32_t)(h * H + k) * gstride];
+      const float w = G[goff + (uint32_t)(h * H + k) * gstride];
       xr[k] *= w;
       xi[k] *= w;
     }
@@ -461,8 +466,8 @@ k_fft_reg(float* __restrict__ grid, GridDims gd, const float* __restrict__ G) {
 #pragma unroll
     for (int k = 0; k < H; ++k) {
       const uint32_t o = lo + (uint32_t)(2 * k + h) * stride;
-      gw[o] = xr[k];
-      gw[o + BG] = xi[k];
+      at(gw, o) = xr[k];
+      at(gw, o + BG) = xi[k];
     }
     return;
   }
@@ -470,22 +475,22 @@ k_fft_reg(float* __restrict__ grid, GridDims gd, const float* __restrict__ G) {
     if (h == 0) {
 #pragma unroll
       for (int k = 0; k < H; ++k) {
-        gw[lo + (uint32_t)(2 * k) * stride] = xr[k];
-        gw[lo + (uint32_t)(2 * k + 1) * stride] = xi[k];
+        at(gw, lo + (uint32_t)(2 * k) * stride) = xr[k];
+        at(gw, lo + (uint32_t)(2 * k + 1) * stride) = xi[k];
       }
     } else {
-      gw[lo + (uint32_t)(2 * H) * stride] = xr[0];
-      gw[lo + (uint32_t)(2 * H + 1) * stride] = xi[0];
+      at(gw, lo + (uint32_t)(2 * H) * stride) = xr[0];
+      at(gw, lo + (uint32_t)(2 * H + 1) * stride) = xi[0];
     }
   } else if (MODE == kXInv) {
 #pragma unroll
-    for (int k = 0; k < H; ++k) gw[lo + (uint32_t)(h * H + k) * stride] = xr[k];
+    for (int k = 0; k < H; ++k) at(gw, lo + (uint32_t)(h * H + k) * stride) = xr[k];
   } else {
 #pragma unroll
     for (int k = 0; k < H; ++k) {
       const uint32_t o = lo + (uint32_t)(h * H + k) * stride;
-      gw[o] = xr[k];
-      gw[o + BG] = xi[k];
+      at(gw, o) = xr[k];
+      at(gw, o + BG) = xi[k];
     }
   }
 }
