@@ -22,4 +22,5 @@ Modules:
   dense    - exact energy from the full spectrum (eqs. plasmonic, plasmonic2)
   replica  - truncated replica sum over periodic images (eq. replica)
   scs      - range-separated self-consistent screening of the polarizabilities (Review section)
+  block_lanczos - block Lanczos quadrature over blocks of b probes
 """
