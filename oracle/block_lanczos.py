@@ -19,8 +19,9 @@ blocks B_k gives the block Gauss rule
 Per probe l, Q_l is the l-th diagonal entry of that b x b matrix; the energy is
 E = 1/2 (D / R) sum_l Q_l - 3/2 sum omega as for single probes (b = 1 reduces to the
 ordinary Lanczos rule). A block whose new residual block is numerically rank
-deficient (a Cholesky pivot of W^T W below (1e-10)^2 max diag) stops there: T is
-truncated to the steps done. No re-orthogonalization (the plain recurrence).
+deficient stops there and T keeps the steps done: a Cholesky pivot of W^T W below
+(1e-10 s)^2, with s = max_i (A_k)_ii the scale of the step (for the probe block, s^2 =
+the largest diagonal entry of V^T V). No re-orthogonalization (the plain recurrence).
 """
 from __future__ import annotations
 
@@ -33,15 +34,15 @@ from .probes import rademacher
 BREAKDOWN = 1e-10
 
 
-def _qr(W: torch.Tensor):
+def _qr(W: torch.Tensor, scale=None):
     """W = Y R with R upper triangular with a positive diagonal (Cholesky of W^T W,
-    twice); None if W^T W is numerically singular."""
+    twice); None if W^T W is numerically singular against the scale."""
     Y, R = W, torch.eye(W.shape[1], dtype=W.dtype)
-    for _ in range(2):
+    for p in range(2):
         G = Y.T @ Y
-        d = torch.diagonal(G)
+        s2 = float(torch.diagonal(G).max()) if (scale is None or p == 1) else scale * scale
         L, info = torch.linalg.cholesky_ex(G)
-        if int(info) != 0 or float(torch.diagonal(L).min() ** 2) <= BREAKDOWN ** 2 * float(d.max()):
+        if int(info) != 0 or float(torch.diagonal(L).min() ** 2) <= BREAKDOWN ** 2 * s2:
             return None
         Rk = L.T
         Y = torch.linalg.solve_triangular(Rk, Y, upper=True, left=False)
@@ -66,7 +67,7 @@ def block_lanczos(matvec: Callable, V: torch.Tensor, m: int):
         W = L - Ys[k] @ As[k]
         if k > 0:
             W = W - Ys[k - 1] @ Bs[k - 1].T
-        q = _qr(W)
+        q = _qr(W, scale=float(torch.diagonal(As[k]).max()))
         if q is None:
             break
         Ys.append(q[0])

@@ -65,6 +65,17 @@ def test_exhausted_krylov_space_is_exact():
     assert torch.allclose(got, want, rtol=1e-10, atol=1e-12)
 
 
+def test_exhausted_space_stops_and_stays_exact():
+    D, b = 12, 4
+    C = _spd(D, seed=5)
+    V = rademacher(3, 0, D // 3, range(b)).reshape(b, D).T
+    As, Bs, R0 = obl.block_lanczos(lambda Y: C @ Y, V, 6)
+    assert len(As) == D // b
+    th, U = torch.linalg.eigh(C)
+    want = V.T @ U @ torch.diag(torch.sqrt(th)) @ U.T @ V
+    assert torch.allclose(obl.block_quadrature(As, Bs, R0), want, rtol=1e-10, atol=1e-12)
+
+
 def test_rank_deficient_residual_stops_the_block():
     D, b = 6, 4
     C = _spd(D, seed=9)
