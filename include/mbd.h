@@ -109,6 +109,15 @@ typedef struct {
                            (energy / energy + forces) and replays it afterwards; the
                            positions may change between calls (mbd_set_positions).
                            Stage timing (mbd_set_timing) runs eagerly instead.           */
+  int32_t krylov_block; /* 0 or 1 => one Lanczos process per probe. 2, 4 or 8 => block
+                           Lanczos on consecutive blocks of that many probes (R and block
+                           must be multiples of it; m * krylov_block <= 512; energy only,
+                           MBD_REORTH_NONE): per probe block V = Y_0 R_0,
+                           A_k = Y_k^T C Y_k, C Y_k - Y_k A_k - Y_{k-1} B_{k-1}^T = Y_{k+1} B_k
+                           (Cholesky QR, twice), and
+                           Q_l = [R_0^T E_1^T sqrt(T) E_1 R_0]_ll with T the block
+                           tridiagonal of the A_k and B_k; the same m matvecs per probe span
+                           a Krylov space krylov_block times wider per block.             */
 } mbd_params;
 
 /* Values derived on the host for one system of a plan. */
@@ -172,7 +181,8 @@ mbd_status mbd_check(mbd_plan plan);
 mbd_status mbd_matvec(mbd_plan plan, int32_t sys, const double* v, double* out,
                       int32_t nrhs, uint32_t components);
 
-/* Lanczos tridiagonals of the last execute (synchronizes). Host arrays:
+/* Lanczos tridiagonals of the last execute (synchronizes; MBD_E_STATE for a plan with
+ * krylov_block > 1, whose projection is block tridiagonal). Host arrays:
  * a [R][m] diagonal, b [R][m] with b[l][k] = b_{k+1} (off-diagonal between k and k+1,
  * b[l][m-1] unused), m_eff [R] steps done before a breakdown. */
 mbd_status mbd_get_tridiagonal(mbd_plan plan, int32_t sys, double* a, double* b,

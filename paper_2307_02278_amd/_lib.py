@@ -48,6 +48,7 @@ class MbdParams(C.Structure):
         ("deterministic", C.c_int32),
         ("replica_cutoff", C.c_double),
         ("graph", C.c_int32),
+        ("krylov_block", C.c_int32),
     ]
 
 

@@ -29,6 +29,7 @@ class Params:
     want_forces: bool = False
     graph: bool = False             # replay execute from a captured HIP graph
     replica_cutoff: float = 0.0     # bohr; > 0 => replica method (float64, energy only)
+    krylov_block: int = 1           # > 1 => block Lanczos over blocks of this many probes
 
     def to_c(self) -> L.MbdParams:
         p = L.MbdParams()
@@ -51,6 +52,7 @@ class Params:
         p.deterministic = 0
         p.graph = 1 if self.graph else 0
         p.replica_cutoff = self.replica_cutoff
+        p.krylov_block = self.krylov_block
         return p
 
 

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libmbd.so")
 HOSTCHECK = os.path.join(HERE, "libmbd_hostcheck.so")
 
 SOURCES = ["api.cpp", "setup.hip", "spme.hip", "fft.hip", "pair.hip", "lanczos.hip",
-           "scs.hip"]
+           "scs.hip", "block.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MBD_OFFLOAD_ARCH", "gfx950")

@@ -193,6 +193,27 @@ void allocate_system(Plan& plan, System& S, int R_probes, int m) {
     b.adj = dalloc<double>(plan, (size_t)B * 16, by);
     b.fsum = dalloc<double>(plan, 3 * (size_t)n, by);
   }
+  if (plan.prm.krylov_block > 1) {
+    BlockWork& bw = b.blk;
+    bw.kb = plan.prm.krylov_block;
+    const size_t nkb = (size_t)B / bw.kb, kk = (size_t)bw.kb * bw.kb;
+    const size_t nt = (size_t)m * bw.kb;
+    bw.nblk = std::max(1, std::min(512, (3 * n + 255) / 256));
+    bw.part = dalloc<double>(plan, (size_t)bw.nblk * B * bw.kb, by);
+    bw.G = dalloc<double>(plan, nkb * kk, by);
+    bw.R1 = dalloc<double>(plan, nkb * kk, by);
+    bw.R0 = dalloc<double>(plan, nkb * kk, by);
+    bw.Atmp = dalloc<double>(plan, nkb * kk, by);
+    bw.Bprev = dalloc<double>(plan, nkb * kk, by);
+    bw.A = dalloc<double>(plan, nkb * m * kk, by);
+    bw.B = dalloc<double>(plan, nkb * m * kk, by);
+    bw.T = dalloc<double>(plan, nkb * nt * nt, by);
+    bw.P = dalloc<double>(plan, nkb * bw.kb * nt, by);
+    bw.d = dalloc<double>(plan, nkb * nt, by);
+    bw.e = dalloc<double>(plan, nkb * nt, by);
+    bw.flag = dalloc<int>(plan, nkb, by);
+    bw.meff = dalloc<int>(plan, nkb, by);
+  }
   std::vector<R> G, tw;
   host_tables<R>(g, G, tw);
   check(hipMemcpy(b.G, G.data(), G.size() * sizeof(R), hipMemcpyHostToDevice), "copy G");
@@ -326,8 +347,41 @@ void matvec_block(Plan& plan, System& S, const double* w, uint32_t comps) {
 template <typename R>
 void run_backward(Plan& plan, System& S, int l0, int nb);
 
+// Block Lanczos (krylov_block > 1): per batch of B probes, B / kb Krylov blocks run
+// side by side through the same matvecs; each block step replaces the scalar update.
+template <typename R>
+void run_energy_block(Plan& plan, System& S, int sys_index, double* energy) {
+  const hipStream_t st = plan.stream;
+  const int B = plan.B, m = plan.prm.n_steps, R_probes = plan.prm.n_probes;
+  const bool fl = sizeof(R) == 4;
+  const size_t vs = 3 * (size_t)S.geo.n * B;
+  const BlockWork& bw = S.buf.blk;
+  for (int l0 = 0; l0 < R_probes; l0 += B) {
+    const int nb = std::min(B, R_probes - l0);
+    staged(plan, MBD_STAGE_LANCZOS, [&] {
+      launch_init_scalars(S.buf, nb, m, l0, st);
+      launch_probes(S.geo, S.buf, B, nb, l0, plan.prm.seed, sys_index, fl, st);
+      launch_block_start(S.geo, S.buf, bw, B, m, fl, st);
+    });
+    for (int k = 0; k < m; ++k) {
+      matvec_block<R>(plan, S, S.buf.W + (size_t)k * vs, MBD_C_ALL);
+      staged(plan, MBD_STAGE_LANCZOS,
+             [&] { launch_block_step(S.geo, S.buf, bw, B, k, m, fl, st); });
+    }
+    staged(plan, MBD_STAGE_LANCZOS, [&] {
+      launch_block_quadrature(bw, nb / bw.kb, m, S.buf.q + l0, plan.status, st);
+    });
+  }
+  staged(plan, MBD_STAGE_LANCZOS,
+         [&] { launch_energy(S.geo, S.buf, R_probes, energy, plan.status, st); });
+}
+
 template <typename R>
 void run_energy(Plan& plan, System& S, int sys_index, double* energy, bool forces) {
+  if (plan.prm.krylov_block > 1) {
+    run_energy_block<R>(plan, S, sys_index, energy);
+    return;
+  }
   const hipStream_t st = plan.stream;
   const int B = plan.B, m = plan.prm.n_steps, R_probes = plan.prm.n_probes;
   const bool fl = sizeof(R) == 4;
@@ -459,6 +513,21 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
     if (prm.want_forces) return fail(MBD_E_ARG, "the replica method has no forces");
     if (prm.block > 8) return fail(MBD_E_ARG, "the replica method needs block <= 8");
   }
+  if (prm.krylov_block == 0) prm.krylov_block = 1;
+  if (prm.krylov_block != 1 && prm.krylov_block != 2 && prm.krylov_block != 4 &&
+      prm.krylov_block != 8)
+    return fail(MBD_E_ARG, "krylov_block must be 0, 1, 2, 4 or 8");
+  if (prm.krylov_block > 1) {
+    const int kb = prm.krylov_block;
+    if (prm.block % kb != 0) return fail(MBD_E_ARG, "block must be a multiple of krylov_block");
+    if (prm.n_probes % kb != 0)
+      return fail(MBD_E_ARG, "n_probes must be a multiple of krylov_block");
+    if (prm.want_forces) return fail(MBD_E_ARG, "block Lanczos plans have no forces");
+    if (prm.reorth != MBD_REORTH_NONE)
+      return fail(MBD_E_ARG, "block Lanczos runs without re-orthogonalization");
+    if (prm.n_steps * kb > kBlockMaxDim)
+      return fail(MBD_E_ARG, "n_steps * krylov_block must be <= 512");
+  }
   for (int a = 0; a < 3; ++a)
     if (prm.grid[a] < 0) return fail(MBD_E_ARG, "grid sizes must be >= 0");
 
@@ -467,6 +536,8 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
   for (int s = 0; s < n_sys; ++s) {
     const mbd_system& sy = systems[s];
     if (sy.n_atoms < 1) return fail(MBD_E_ARG, "n_atoms must be >= 1");
+    if (3 * sy.n_atoms < prm.krylov_block)
+      return fail(MBD_E_ARG, "krylov_block exceeds the dimension 3N of a system");
     if (!sy.pos || !sy.alpha || !sy.omega || !sy.r_vdw)
       return fail(MBD_E_ARG, "system arrays must be non-NULL device pointers");
     for (int i = 0; i < 9; ++i)
@@ -859,6 +930,8 @@ mbd_status mbd_get_tridiagonal(mbd_plan plan, int32_t sys, double* a, double* b,
   mbd::Plan& P = plan->plan;
   if (sys < 0 || sys >= (int)P.sys.size()) return fail(MBD_E_ARG, "system index out of range");
   if (!P.executed) return fail(MBD_E_STATE, "no execute has run");
+  if (P.prm.krylov_block > 1)
+    return fail(MBD_E_STATE, "a block Lanczos plan has a block tridiagonal");
   const int R = P.prm.n_probes, m = P.prm.n_steps;
   const mbd::SysBuffers& B = P.sys[sys].buf;
   std::vector<double> nrm((size_t)R * m);

@@ -78,6 +78,26 @@ __host__ __device__ inline void cell_coords(int c, int& cx, int& cy, int& cz) {
 }
 inline int cell_slots(const Geometry& g) { return 1 << (3 * g.mbits); }
 
+// block Lanczos quadrature (kb probes per Krylov block)
+constexpr int kBlockMaxDim = 512;  // largest m kb (dimension of the block tridiagonal)
+struct BlockWork {
+  int kb = 1;               // probes per Krylov block (2, 4 or 8)
+  int nblk = 0;             // row blocks of the Gram reductions
+  double* part = nullptr;   // [nblk][B kb] partial Gram sums
+  double* G = nullptr;      // [B / kb][kb][kb] Gram matrices
+  double* R1 = nullptr;     // [B / kb][kb][kb] Cholesky factor of the current pass
+  double* R0 = nullptr;     // [B / kb][kb][kb] probe block = Y_0 R0
+  double* Atmp = nullptr;   // [B / kb][kb][kb] A_k of the current step
+  double* Bprev = nullptr;  // [B / kb][kb][kb] B_k of the current step
+  double* A = nullptr;      // [B / kb][m][kb][kb]
+  double* B = nullptr;      // [B / kb][m][kb][kb]
+  double* T = nullptr;      // [B / kb][m kb][m kb] eigen workspace
+  double* P = nullptr;      // [B / kb][kb][m kb]
+  double* d = nullptr;      // [B / kb][m kb]
+  double* e = nullptr;      // [B / kb][m kb]
+  int* flag = nullptr;      // [B / kb] block ended (rank-deficient residual)
+  int* meff = nullptr;      // [B / kb] block steps kept
+};
 // Device buffers of one system.
 struct SysBuffers {
   // sorted atom data
@@ -130,6 +150,7 @@ struct SysBuffers {
   double* bbar = nullptr;      // [B][m] dQ/d nrm_k (k >= 1)
   double* adj = nullptr;       // [B][8] per-step adjoint scalars
   double* fsum = nullptr;      // [n][3] sum over probes and steps of l-bar^T dC/dR y (sorted)
+  BlockWork blk;               // block Lanczos workspace (krylov_block > 1)
 };
 
 struct System {
@@ -269,6 +290,13 @@ void launch_scs_iteration(const Geometry& g, const SysBuffers& b, const ScsWork&
 void launch_scs_output(const SysBuffers& b, const ScsWork& w, const double* wq,
                        const double* alpha, const double* rvdw, double* a_out, double* om_out,
                        double* rv_out, double* af_out, hipStream_t st);
+
+void launch_block_start(const Geometry& geo, const SysBuffers& b, const BlockWork& bw, int B,
+                        int m, bool use_float, hipStream_t st);
+void launch_block_step(const Geometry& geo, const SysBuffers& b, const BlockWork& bw, int B,
+                       int k, int m, bool use_float, hipStream_t st);
+void launch_block_quadrature(const BlockWork& bw, int nkb, int m, double* q_out,
+                             uint32_t* status, hipStream_t st);
 
 bool fft_supported(int k);
 void set_error(const std::string& msg);

@@ -295,6 +295,52 @@ MBD_HD int tridiag_eigen(double* d, double* e, double* u, int n, int ld) {
   return 1;
 }
 
+// Same iteration, applying every rotation to the columns of a given nrows x n matrix P
+// (row-major, leading dimension ld): on return d holds the eigenvalues and P has become
+// P U, U the eigenvector matrix of the tridiagonal. Returns 0 if it did not converge.
+MBD_HD int tridiag_eigen_rows(double* d, double* e, double* P, int n, int nrows, int ld) {
+  int hi = n - 1;
+  int iter = 0;
+  const double eps = 2.220446049250313e-16;
+  while (hi > 0) {
+    if (fabs(e[hi - 1]) <= eps * (fabs(d[hi - 1]) + fabs(d[hi]))) {
+      e[hi - 1] = 0.0;
+      --hi;
+      continue;
+    }
+    int lo = hi - 1;
+    while (lo > 0 && fabs(e[lo - 1]) > eps * (fabs(d[lo - 1]) + fabs(d[lo]))) --lo;
+    if (++iter > 60 * n) return 0;
+    const double delta = 0.5 * (d[hi - 1] - d[hi]);
+    const double eh = e[hi - 1];
+    const double den = delta + (delta >= 0.0 ? 1.0 : -1.0) * sqrt(delta * delta + eh * eh);
+    const double mu = (den != 0.0) ? d[hi] - eh * eh / den : d[hi];
+    double x = d[lo] - mu;
+    double z = e[lo];
+    for (int k = lo; k < hi; ++k) {
+      const double r = hypot(x, z);
+      double c = 1.0, s = 0.0;
+      if (r != 0.0) { c = x / r; s = -z / r; }
+      if (k > lo) e[k - 1] = r;
+      const double dk = d[k], dk1 = d[k + 1], ek = e[k];
+      d[k] = c * c * dk - 2.0 * c * s * ek + s * s * dk1;
+      d[k + 1] = s * s * dk + 2.0 * c * s * ek + c * c * dk1;
+      e[k] = c * s * (dk - dk1) + (c * c - s * s) * ek;
+      if (k + 1 < hi) {
+        z = -s * e[k + 1];
+        e[k + 1] = c * e[k + 1];
+        x = e[k];
+      }
+      for (int i = 0; i < nrows; ++i) {
+        const double a0 = P[i * ld + k], a1 = P[i * ld + k + 1];
+        P[i * ld + k] = c * a0 - s * a1;
+        P[i * ld + k + 1] = s * a0 + c * a1;
+      }
+    }
+  }
+  return 1;
+}
+
 // Adjoint of the Gauss quadrature Q = e1^T sqrt(T) e1 with respect to the
 // tridiagonal T = U diag(theta) U^T: dQ/dT = U (F o c c^T) U^T with c = U^T e1 and the
 // divided differences F_ij = 1 / (sqrt(theta_i) + sqrt(theta_j)) of the square root

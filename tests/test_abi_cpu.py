@@ -94,6 +94,13 @@ def _create(s, p, nsys=1):
     (lambda s, p: setattr(p, "reorth", 9), L.MBD_E_ARG),
     (lambda s, p: setattr(p, "want_forces", 2), L.MBD_E_ARG),
     (lambda s, p: (setattr(p, "want_forces", 1), setattr(p, "block", 2)), L.MBD_E_ARG),
+    (lambda s, p: setattr(p, "krylov_block", 3), L.MBD_E_ARG),
+    (lambda s, p: setattr(p, "krylov_block", 8), L.MBD_E_ARG),      # block 4 < 8
+    (lambda s, p: (setattr(p, "krylov_block", 4), setattr(p, "n_probes", 6)), L.MBD_E_ARG),
+    (lambda s, p: (setattr(p, "krylov_block", 2), setattr(p, "reorth", 2)), L.MBD_E_ARG),
+    (lambda s, p: (setattr(p, "krylov_block", 4), setattr(p, "want_forces", 1)), L.MBD_E_ARG),
+    (lambda s, p: (setattr(p, "krylov_block", 4), setattr(p, "n_steps", 200)), L.MBD_E_ARG),
+    (lambda s, p: (setattr(p, "krylov_block", 4), setattr(s, "n_atoms", 1)), L.MBD_E_ARG),
     (lambda s, p: setattr(s, "n_atoms", 0), L.MBD_E_ARG),
     (lambda s, p: setattr(s, "pos", None), L.MBD_E_ARG),
     (lambda s, p: [s.cell.__setitem__(3 + c, s.cell[c]) for c in range(3)], L.MBD_E_CELL),
