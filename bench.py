@@ -215,6 +215,50 @@ def scs_timing(plan, torch, s, n_pairs, n_freq=15):
             "alpha_scs_over_alpha": [round(float(ratio.min()), 4), round(float(ratio.max()), 4)]}
 
 
+def block_study(P, torch, synth):
+    """Quadrature error per probe at a fixed number of matvecs: single-probe Lanczos
+    against block Lanczos (krylov_block 4 and 8) with the same probes and the same m,
+    on the 24k water box in mixed precision; the reference is single-probe Lanczos with
+    full re-orthogonalization at m = 120. Also the wall time of one execute."""
+    wl = synth.workload("batched24k")
+    s = wl.systems[0]
+    A = synth.ANGSTROM_BOHR
+    K = tuple(wl.grid) * 3 if len(wl.grid) == 1 else tuple(wl.grid)
+    ds = P.DeviceSystem(s.pos, s.cell, s.alpha, s.omega, s.rvdw)
+    R = 64
+
+    def run(m, kb=1, reorth=P.REORTH_NONE):
+        plan = P.Plan([ds], P.Params(real_cutoff=wl.real_cutoff_angstrom * A, grid=K,
+                                     n_probes=R, n_steps=m, block=R, precision=P.PREC_MIXED,
+                                     seed=wl.probe_seed, reorth=reorth, krylov_block=kb))
+        plan.execute()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.execute()
+        torch.cuda.synchronize()
+        ms = 1000.0 * (time.perf_counter() - t0)
+        plan.check()
+        q = plan.quadrature()
+        plan.close()
+        return q, ms
+
+    qref, _ = run(120, 1, P.REORTH_FULL)
+    rows = []
+    for m in (3, 4, 6, 8, 12, 16):
+        for kb in (1, 4, 8):
+            q, ms = run(m, kb)
+            rel = ((q - qref).abs() / qref.abs())
+            rows.append({"m": m, "krylov_block": kb, "max_rel_err": float(rel.max()),
+                         "mean_rel_err": float(rel.mean()),
+                         "trace_rel_err": float(abs(q.sum() - qref.sum()) / qref.sum()),
+                         "execute_ms": round(ms, 2)})
+            log(f"block study m={m} kb={kb}: max rel err {float(rel.max()):.2e}, "
+                f"{ms:.1f} ms")
+    return {"workload": "water box N=24000, 64 probes, mixed precision",
+            "reference": "single-probe Lanczos, full re-orthogonalization, m = 120",
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +277,9 @@ def main():
                     help="launch every kernel from the host instead of replaying HIP graphs")
     ap.add_argument("--no-scs", action="store_true",
                     help="skip the self-consistent screening leg on the 24k box")
+    ap.add_argument("--block-study", action="store_true",
+                    help="also compare single-probe and block Lanczos quadrature errors at "
+                         "equal matvec counts on the 24k box")
     ap.add_argument("--delta11", action="store_true",
                     help="also run the Delta_11 convergence study (SPME vs grid, replica vs "
                          "cutoff) on a 216-water box and a 512-atom diamond box")
@@ -366,6 +413,7 @@ def main():
     uneven_leg = energy_forces_leg(P, torch, synth, "uneven", False) if args.uneven else None
 
     d11 = delta11_study(P, torch, synth) if args.delta11 else None
+    bstudy = block_study(P, torch, synth) if args.block_study else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -419,6 +467,8 @@ def main():
         out["energy_forces_uneven"] = uneven_leg
     if d11 is not None:
         out["delta11"] = d11
+    if bstudy is not None:
+        out["block_study"] = bstudy
     print(json.dumps(out), flush=True)
 
 
