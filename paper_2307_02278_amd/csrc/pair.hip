@@ -98,141 +98,214 @@ k_pair_direct(const Geometry geo, const int* __restrict__ cell_start,
 // Tensor list: build (once per device setup) and apply (every matvec).
 // ---------------------------------------------------------------------------
 
-// One wavefront per group of kGroup consecutive sorted targets. Candidate sources
-// are the atoms of the cells around the group whose distance to the group's
-// bounding box is below r_pair; those within r_pair of at least one target are
-// appended (wavefront ballot, fixed order) with their tensors. With cap == 0 only
-// the counts are produced (plan sizing).
+// One work-group (256 threads) per group of kGroup consecutive sorted targets.
+// Candidate sources are the atoms of the cells around the group whose distance to
+// the group's bounding box is below r_pair; those within r_pair of at least one
+// target are appended with their tensors, in the order of the cell scan (z, y, x,
+// then atom index). The cells are taken in chunks: their atom counts are prefix-summed
+// in LDS, every thread tests one candidate of a 256-candidate round, the hits are
+// compacted in order (wavefront ballots plus a prefix over the four wavefronts), and
+// the tensors of a round are then written with one thread per (candidate, target)
+// pair, so that consecutive threads store consecutive tensor words. With cap == 0
+// only the counts are produced (plan sizing).
+constexpr int kBuildCells = 256;  // cells per chunk of the scan
 template <typename R>
 __global__ void __launch_bounds__(256)
 k_pair_build(const Geometry geo, const int* __restrict__ cell_start,
              const int* __restrict__ scell, const R* __restrict__ loc, int cap,
              int2* __restrict__ hdr, R* __restrict__ Tg, R* __restrict__ Fg,
              int* __restrict__ gcount, int* __restrict__ maxcount) {
-  __shared__ R tgt_all[4][kGroup][4];
-  __shared__ int tcell_all[4][kGroup][3];
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-  const int lane = threadIdx.x & 63;
-  const int group = blockIdx.x * 4 + wave;
+  __shared__ R tgt[kGroup][4];
+  __shared__ int tcell[kGroup][3];
+  __shared__ int red_i[6];
+  __shared__ R red_r[6];
+  __shared__ int c_pre[kBuildCells + 1];   // prefix of the chunk's cell atom counts
+  __shared__ int c_first[kBuildCells];     // first atom of each cell
+  __shared__ int c_off[kBuildCells];       // packed (dx, dy, dz) cell offsets
+  __shared__ int wcnt[4];
+  __shared__ R s_p[256][4];                // compacted hits of a round: position, radius
+  __shared__ int s_m[256];                 // their target masks
+  __shared__ int s_o[256];                 // their packed cell offsets
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int group = blockIdx.x;
   const int g0 = group * kGroup;
-  if (g0 >= geo.n) return;
   const int n = geo.n;
   const int nc0 = geo.nc[0], nc1 = geo.nc[1], nc2 = geo.nc[2];
-  R(*tgt)[4] = tgt_all[wave];
-  int(*tcell)[3] = tcell_all[wave];
-
-  // targets relative to the cell of the group's first atom
-  const int ti = g0 + (lane & 15);
-  const bool tvalid = ti < n;
-  int c0x, c0y, c0z, tcx, tcy, tcz;
+  int c0x, c0y, c0z;
   cell_coords(scell[g0], c0x, c0y, c0z);
-  cell_coords(scell[tvalid ? ti : g0], tcx, tcy, tcz);
-  const int dcx = tcx - c0x, dcy = tcy - c0y, dcz = tcz - c0z;
-  const R* tl = loc + 4 * (size_t)(tvalid ? ti : g0);
-  // target position relative to the corner of the group's first cell
-  const R tx = tl[0] + (R)(dcx * geo.hv[0][0] + dcy * geo.hv[1][0] + dcz * geo.hv[2][0]);
-  const R ty = tl[1] + (R)(dcx * geo.hv[0][1] + dcy * geo.hv[1][1] + dcz * geo.hv[2][1]);
-  const R tz = tl[2] + (R)(dcx * geo.hv[0][2] + dcy * geo.hv[1][2] + dcz * geo.hv[2][2]);
-  if (lane < kGroup) {
-    tgt[lane][0] = tx; tgt[lane][1] = ty; tgt[lane][2] = tz; tgt[lane][3] = tl[3];
-    tcell[lane][0] = dcx; tcell[lane][1] = dcy; tcell[lane][2] = dcz;
-  }
-  // bounding box of the valid targets and their cell-offset range
-  R bx0 = tx, bx1 = tx, by0 = ty, by1 = ty, bz0 = tz, bz1 = tz;
-  int mx0 = dcx, mx1 = dcx, my0 = dcy, my1 = dcy, mz0 = dcz, mz1 = dcz;
-  for (int off = 1; off < 16; off <<= 1) {
-    bx0 = min(bx0, __shfl_xor(bx0, off)); bx1 = max(bx1, __shfl_xor(bx1, off));
-    by0 = min(by0, __shfl_xor(by0, off)); by1 = max(by1, __shfl_xor(by1, off));
-    bz0 = min(bz0, __shfl_xor(bz0, off)); bz1 = max(bz1, __shfl_xor(bz1, off));
-    mx0 = min(mx0, __shfl_xor(mx0, off)); mx1 = max(mx1, __shfl_xor(mx1, off));
-    my0 = min(my0, __shfl_xor(my0, off)); my1 = max(my1, __shfl_xor(my1, off));
-    mz0 = min(mz0, __shfl_xor(mz0, off)); mz1 = max(mz1, __shfl_xor(mz1, off));
-  }
-  // all lanes now agree (every lane reduced over the same 16 target copies)
-  __builtin_amdgcn_wave_barrier();
   const int ntg = min(kGroup, n - g0);
+  // targets relative to the corner of the group's first cell
+  if (tid < kGroup) {
+    const int ti = g0 + (tid < ntg ? tid : 0);
+    int tcx, tcy, tcz;
+    cell_coords(scell[ti], tcx, tcy, tcz);
+    const int dcx = tcx - c0x, dcy = tcy - c0y, dcz = tcz - c0z;
+    const R* tl = loc + 4 * (size_t)ti;
+    tgt[tid][0] = tl[0] + (R)(dcx * geo.hv[0][0] + dcy * geo.hv[1][0] + dcz * geo.hv[2][0]);
+    tgt[tid][1] = tl[1] + (R)(dcx * geo.hv[0][1] + dcy * geo.hv[1][1] + dcz * geo.hv[2][1]);
+    tgt[tid][2] = tl[2] + (R)(dcx * geo.hv[0][2] + dcy * geo.hv[1][2] + dcz * geo.hv[2][2]);
+    tgt[tid][3] = tl[3];
+    tcell[tid][0] = dcx; tcell[tid][1] = dcy; tcell[tid][2] = dcz;
+  }
+  __syncthreads();
+  // bounding box of the targets and their cell-offset range (wavefront 0 reduces)
+  if (wave == 0) {
+    const int t = lane < ntg ? lane : 0;
+    R b0 = tgt[t][0], b1 = tgt[t][0], b2 = tgt[t][1], b3 = tgt[t][1], b4 = tgt[t][2],
+      b5 = tgt[t][2];
+    int m0 = tcell[t][0], m1 = tcell[t][0], m2 = tcell[t][1], m3 = tcell[t][1],
+        m4 = tcell[t][2], m5 = tcell[t][2];
+    for (int off = 1; off < 16; off <<= 1) {
+      b0 = min(b0, __shfl_xor(b0, off)); b1 = max(b1, __shfl_xor(b1, off));
+      b2 = min(b2, __shfl_xor(b2, off)); b3 = max(b3, __shfl_xor(b3, off));
+      b4 = min(b4, __shfl_xor(b4, off)); b5 = max(b5, __shfl_xor(b5, off));
+      m0 = min(m0, __shfl_xor(m0, off)); m1 = max(m1, __shfl_xor(m1, off));
+      m2 = min(m2, __shfl_xor(m2, off)); m3 = max(m3, __shfl_xor(m3, off));
+      m4 = min(m4, __shfl_xor(m4, off)); m5 = max(m5, __shfl_xor(m5, off));
+    }
+    if (lane == 0) {
+      red_r[0] = b0; red_r[1] = b1; red_r[2] = b2;
+      red_r[3] = b3; red_r[4] = b4; red_r[5] = b5;
+      red_i[0] = m0; red_i[1] = m1; red_i[2] = m2;
+      red_i[3] = m3; red_i[4] = m4; red_i[5] = m5;
+    }
+  }
+  __syncthreads();
+  const R bx0 = red_r[0], bx1 = red_r[1], by0 = red_r[2], by1 = red_r[3];
+  const R bz0 = red_r[4], bz1 = red_r[5];
+  const int dx0 = red_i[0] - geo.nr[0], dx1 = red_i[1] + geo.nr[0];
+  const int dy0 = red_i[2] - geo.nr[1], dy1 = red_i[3] + geo.nr[1];
+  const int dz0 = red_i[4] - geo.nr[2], dz1 = red_i[5] + geo.nr[2];
+  const int nx = dx1 - dx0 + 1, ny = dy1 - dy0 + 1, nz = dz1 - dz0 + 1;
+  const int ncells = nx * ny * nz;
   const R tau = (R)geo.tau, dd = (R)geo.damp_d;
   const R rp2 = (R)(geo.r_pair * geo.r_pair);
   int count = 0;
-  for (int dz = mz0 - geo.nr[2]; dz <= mz1 + geo.nr[2]; ++dz) {
-    int wz = (c0z + dz) % nc2;
-    if (wz < 0) wz += nc2;
-    for (int dy = my0 - geo.nr[1]; dy <= my1 + geo.nr[1]; ++dy) {
-      int wy = (c0y + dy) % nc1;
-      if (wy < 0) wy += nc1;
-      for (int dx = mx0 - geo.nr[0]; dx <= mx1 + geo.nr[0]; ++dx) {
-        int wx = (c0x + dx) % nc0;
-        if (wx < 0) wx += nc0;
-        const int cc = cell_index(wx, wy, wz);
-        const int j0 = cell_start[cc], j1 = cell_start[cc + 1];
+  for (int cc0 = 0; cc0 < ncells; cc0 += kBuildCells) {
+    const int ncc = min(kBuildCells, ncells - cc0);
+    __syncthreads();  // the previous chunk's tables are no longer read
+    int cnt_cell = 0;
+    if (tid < ncc) {
+      const int ci = cc0 + tid;  // scan order: z outermost, then y, then x
+      const int dx = dx0 + ci % nx, dy = dy0 + (ci / nx) % ny, dz = dz0 + ci / (nx * ny);
+      int wx = (c0x + dx) % nc0; if (wx < 0) wx += nc0;
+      int wy = (c0y + dy) % nc1; if (wy < 0) wy += nc1;
+      int wz = (c0z + dz) % nc2; if (wz < 0) wz += nc2;
+      const int cc = cell_index(wx, wy, wz);
+      c_first[tid] = cell_start[cc];
+      cnt_cell = cell_start[cc + 1] - cell_start[cc];
+      c_off[tid] = ((dx + 512) << 20) | ((dy + 512) << 10) | (dz + 512);
+    }
+    // prefix of the counts: scan within each wavefront, then the wavefront offsets
+    int v = cnt_cell;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(v, o);
+      if (lane >= o) v += u;
+    }
+    if (lane == 63) wcnt[wave] = v;
+    __syncthreads();
+    int woff = 0;
+    for (int w = 0; w < wave; ++w) woff += wcnt[w];
+    if (tid < ncc) c_pre[tid + 1] = v + woff;
+    if (tid == 0) c_pre[0] = 0;
+    __syncthreads();
+    const int total = c_pre[ncc];
+    for (int r0 = 0; r0 < total; r0 += 256) {
+      const int c = r0 + tid;
+      uint32_t mask = 0;
+      R px = R(0), py = R(0), pz = R(0), ps = R(0);
+      int off = 0, j = 0;
+      if (c < total) {
+        // the cell holding candidate c: largest k with c_pre[k] <= c
+        int lo = 0, hi = ncc - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (c_pre[mid] <= c) lo = mid; else hi = mid - 1;
+        }
+        j = c_first[lo] + (c - c_pre[lo]);
+        off = c_off[lo];
+        const int dx = (off >> 20) - 512, dy = ((off >> 10) & 1023) - 512,
+                  dz = (off & 1023) - 512;
         const R sx = (R)(dx * geo.hv[0][0] + dy * geo.hv[1][0] + dz * geo.hv[2][0]);
         const R sy = (R)(dx * geo.hv[0][1] + dy * geo.hv[1][1] + dz * geo.hv[2][1]);
         const R sz = (R)(dx * geo.hv[0][2] + dy * geo.hv[1][2] + dz * geo.hv[2][2]);
-        for (int jb = j0; jb < j1; jb += 64) {
-          const int j = jb + lane;
-          uint32_t mask = 0;
-          R px = R(0), py = R(0), pz = R(0), ps = R(0);
-          if (j < j1) {
-            px = loc[4 * (size_t)j] + sx;
-            py = loc[4 * (size_t)j + 1] + sy;
-            pz = loc[4 * (size_t)j + 2] + sz;
-            ps = loc[4 * (size_t)j + 3];
-            const R ex = max(max(bx0 - px, px - bx1), R(0));
-            const R ey = max(max(by0 - py, py - by1), R(0));
-            const R ez = max(max(bz0 - pz, pz - bz1), R(0));
-            if (ex * ex + ey * ey + ez * ez < rp2) {
-              for (int t = 0; t < ntg; ++t) {
-                const R rx = px - tgt[t][0], ry = py - tgt[t][1], rz = pz - tgt[t][2];
-                const bool self = (j == g0 + t) && dx == tcell[t][0] && dy == tcell[t][1] &&
-                                  dz == tcell[t][2];
-                if (!self && rx * rx + ry * ry + rz * rz < rp2) mask |= 1u << t;
-              }
-            }
+        px = loc[4 * (size_t)j] + sx;
+        py = loc[4 * (size_t)j + 1] + sy;
+        pz = loc[4 * (size_t)j + 2] + sz;
+        ps = loc[4 * (size_t)j + 3];
+        const R ex = max(max(bx0 - px, px - bx1), R(0));
+        const R ey = max(max(by0 - py, py - by1), R(0));
+        const R ez = max(max(bz0 - pz, pz - bz1), R(0));
+        if (ex * ex + ey * ey + ez * ez < rp2) {
+          for (int t = 0; t < ntg; ++t) {
+            const R rx = px - tgt[t][0], ry = py - tgt[t][1], rz = pz - tgt[t][2];
+            const bool self = (j == g0 + t) && dx == tcell[t][0] && dy == tcell[t][1] &&
+                              dz == tcell[t][2];
+            if (!self && rx * rx + ry * ry + rz * rz < rp2) mask |= 1u << t;
           }
-          const unsigned long long bal = __ballot(mask != 0u);
-          const int nk = __popcll(bal);
-          if (nk == 0) continue;
-          const int slot = count + (int)__builtin_amdgcn_mbcnt_hi(
-                                       (unsigned)(bal >> 32),
-                                       __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
-          if (mask != 0u && slot < cap) {
-            const size_t e = (size_t)group * cap + slot;
-            hdr[e] = make_int2(j, (int)mask);
-            R* T = Tg + e * kCandStride;
-            for (int t = 0; t < kGroup; ++t) {
-              R A = R(0), Bk = R(0), rx = R(0), ry = R(0), rz = R(0);
-              if ((mask >> t) & 1u) {
-                rx = px - tgt[t][0]; ry = py - tgt[t][1]; rz = pz - tgt[t][2];
-                direct_kernel<R>(rx * rx + ry * ry + rz * rz, tau, R(1) / (ps + tgt[t][3]), dd,
-                                 A, Bk);
-              }
-              R* o = T + t * kTensorWords;
-              o[0] = A - Bk * rx * rx;
-              o[1] = A - Bk * ry * ry;
-              o[2] = A - Bk * rz * rz;
-              o[3] = -Bk * rx * ry;
-              o[4] = -Bk * rx * rz;
-              o[5] = -Bk * ry * rz;
-              if (Fg) {
-                // radial data for forces, evaluated in double precision
-                double Ad = 0.0, Bd = 0.0, dA = 0.0, dB = 0.0;
-                if ((mask >> t) & 1u) {
-                  const double r2 = (double)rx * rx + (double)ry * ry + (double)rz * rz;
-                  direct_kernel_grad(r2, geo.tau, 1.0 / ((double)ps + (double)tgt[t][3]),
-                                     geo.damp_d, Ad, Bd, dA, dB);
-                }
-                R* f = Fg + e * kCandStride + t * kTensorWords;
-                f[0] = rx; f[1] = ry; f[2] = rz;
-                f[3] = (R)Bd; f[4] = (R)dA; f[5] = (R)dB;
-              }
-            }
-          }
-          count += nk;
         }
       }
+      // in-order compaction of the hits
+      const unsigned long long bal = __ballot(mask != 0u);
+      const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+      if (lane == 0) wcnt[wave] = __popcll(bal);
+      __syncthreads();
+      int wpre = 0;
+      for (int w = 0; w < wave; ++w) wpre += wcnt[w];
+      const int nloc = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+      if (mask != 0u) {
+        const int li = wpre + below;
+        s_p[li][0] = px; s_p[li][1] = py; s_p[li][2] = pz; s_p[li][3] = ps;
+        s_m[li] = (int)mask;
+        s_o[li] = off;
+        const int slot = count + li;
+        if (slot < cap) hdr[(size_t)group * cap + slot] = make_int2(j, (int)mask);
+      }
+      __syncthreads();
+      if (cap > 0) {
+        // tensors of the round's hits: thread <-> (hit, target)
+        for (int p = tid; p < nloc * kGroup; p += 256) {
+          const int li = p / kGroup, t = p % kGroup;
+          const int slot = count + li;
+          if (slot >= cap) continue;
+          const uint32_t mk = (uint32_t)s_m[li];
+          R A = R(0), Bk = R(0), rx = R(0), ry = R(0), rz = R(0);
+          const R qx = s_p[li][0], qy = s_p[li][1], qz = s_p[li][2], qs = s_p[li][3];
+          if ((mk >> t) & 1u) {
+            rx = qx - tgt[t][0]; ry = qy - tgt[t][1]; rz = qz - tgt[t][2];
+            direct_kernel<R>(rx * rx + ry * ry + rz * rz, tau, R(1) / (qs + tgt[t][3]), dd,
+                             A, Bk);
+          }
+          const size_t e = (size_t)group * cap + slot;
+          R* o = Tg + e * kCandStride + t * kTensorWords;
+          o[0] = A - Bk * rx * rx;
+          o[1] = A - Bk * ry * ry;
+          o[2] = A - Bk * rz * rz;
+          o[3] = -Bk * rx * ry;
+          o[4] = -Bk * rx * rz;
+          o[5] = -Bk * ry * rz;
+          if (Fg) {
+            // radial data for forces, evaluated in double precision
+            double Ad = 0.0, Bd = 0.0, dA = 0.0, dB = 0.0;
+            if ((mk >> t) & 1u) {
+              const double r2 = (double)rx * rx + (double)ry * ry + (double)rz * rz;
+              direct_kernel_grad(r2, geo.tau, 1.0 / ((double)qs + (double)tgt[t][3]),
+                                 geo.damp_d, Ad, Bd, dA, dB);
+            }
+            R* f = Fg + e * kCandStride + t * kTensorWords;
+            f[0] = rx; f[1] = ry; f[2] = rz;
+            f[3] = (R)Bd; f[4] = (R)dA; f[5] = (R)dB;
+          }
+        }
+      }
+      count += nloc;
+      __syncthreads();  // the round's staging is free again
     }
   }
-  if (lane == 0) {
+  if (tid == 0) {
     gcount[group] = count;
     atomicMax(maxcount, count);
   }
@@ -617,7 +690,7 @@ template <typename R>
 void launch_pair_build(const Geometry& g, const SysBuffers& b, bool count_only, hipStream_t st) {
   const int ngroups = (g.n + kGroup - 1) / kGroup;
   fill_int(b.pg_max, 0, 1, st);
-  k_pair_build<R><<<(ngroups + 3) / 4, 256, 0, st>>>(
+  k_pair_build<R><<<ngroups, 256, 0, st>>>(
       g, b.cell_start, b.scell, (const R*)b.loc, count_only ? 0 : b.pg_cap, b.pg_hdr,
       (R*)b.pg_T, count_only ? nullptr : (R*)b.pg_F, b.pg_count, b.pg_max);
 }
