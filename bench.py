@@ -38,8 +38,10 @@ def log(*a):
 
 
 # Kernel that implements each timed stage at this workload (float, p = 6, 64-wide chunks).
+# Kernel instance behind each stage at the 24k workload (B = 128: the dispatch picks two
+# target subsets per wavefront and four wavefronts per group, as the kernel trace shows).
 STAGE_KERNEL = {
-    "pair": "k_pair_list<float, 1, 2>", "spread": "k_spread<float, 6, 64>",
+    "pair": "k_pair_list<float, 2, 4>", "spread": "k_spread<float, 6, 64>",
     "fft_x": "k_fft_reg<96, 0>", "fft_y": "k_fft_reg<96, 1>", "fft_z_conv": "k_fft_reg<96, 2>",
     "ifft_y": "k_fft_reg<96, 3>", "ifft_x": "k_fft_reg<96, 4>",
     "gather": "k_gather_epilogue<float, 6, 64>",
