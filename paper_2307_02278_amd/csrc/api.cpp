@@ -1012,6 +1012,7 @@ mbd_status mbd_scs(mbd_plan plan, int32_t sys, const mbd_scs_params* prm_in, dou
     w.p = alloc(vec);
     w.q = alloc(vec);
     w.part = alloc((size_t)w.nblk * 2 * w.ncol);
+    w.sums = alloc(2 * (size_t)w.ncol);
     w.sc = alloc(8 * (size_t)w.ncol);
     w.nact = reinterpret_cast<int*>(alloc(1));
     double* u_d = alloc(w.nq);

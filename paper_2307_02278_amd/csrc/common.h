@@ -276,6 +276,7 @@ struct ScsWork {
   double* sig2 = nullptr;   // [n][nq] sigma_i(u_q)^2
   double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;  // [n][3][ncol]
   double* part = nullptr;   // [nblk][2][ncol] partial dot products
+  double* sums = nullptr;   // [2][ncol] their column sums
   double* sc = nullptr;     // [8][ncol] CG scalars
   int* nact = nullptr;      // [1] columns still iterating
 };

@@ -26,6 +26,9 @@ namespace {
 constexpr double kTwoOverSqrtPi = 1.1283791670955126;
 // 1 - f = 1 / (1 + e^z) is below 1e-16 for z > 36.8: such pairs add nothing in float64
 constexpr double kDampSkip = 36.8;
+// Beyond r = 7 sigma_ij, erf(z) = 1 and c (3 + 2 z^2) < 1e-18 in float64: T_GG is the bare
+// tensor A = 1/r^3, B = 3/r^5 to the last bit.
+constexpr double kCloudFar2 = 49.0;
 
 // CG scalar rows of ScsWork::sc ([kScsRows][ncol])
 enum { kRz = 0, kPq = 1, kAlpha = 2, kBeta = 3, kRr = 4, kActive = 5, kBb = 6, kScsRows = 8 };
@@ -113,13 +116,18 @@ k_scs_apply(const Geometry geo, const int* __restrict__ cell_start,
           const double zf = dd * (r / (Si + locd[4 * j + 3]) - 1.0);
           if (zf > kDampSkip || !fv) continue;
           const double omf = 1.0 / (1.0 + exp(zf));
-          const double z = r / sqrt(s2i + sig2[(size_t)j * nq + f]);
-          const double c = kTwoOverSqrtPi * z * exp(-z * z);
-          const double er = erf(z);
+          const double z2 = r2 / (s2i + sig2[(size_t)j * nq + f]);
           const double ir2 = 1.0 / r2;
           const double ir3 = ir2 / r;
-          const double A = omf * (er - c) * ir3;
-          const double Bk = omf * (3.0 * er - c * (3.0 + 2.0 * z * z)) * ir3 * ir2;
+          double A = omf * ir3, Bk = 3.0 * omf * ir3 * ir2;
+          if (z2 < kCloudFar2) {
+            // clouds still overlap: T_GG differs from the bare tensor
+            const double z = sqrt(z2);
+            const double c = kTwoOverSqrtPi * z * exp(-z2);
+            const double er = erf(z);
+            A = omf * (er - c) * ir3;
+            Bk = omf * (3.0 * er - c * (3.0 + 2.0 * z2)) * ir3 * ir2;
+          }
           const double* pj = p + (size_t)j * 3 * ncol + 3 * f;
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
@@ -207,15 +215,36 @@ __global__ void k_scs_init(int n, int nq, const double* __restrict__ ainv, doubl
   }
 }
 
-// One block of ncol threads: sum the partials of nblk blocks in order.
-__device__ inline void sum_parts(const double* part, int nblk, int ncol, int c, double& v1,
-                                 double& v2) {
-  v1 = 0.0;
-  v2 = 0.0;
-  for (int b = 0; b < nblk; ++b) {
+// sums[k][c] = sum over the nblk row blocks of part[b][k][c] (k = 0, 1): one work-group
+// per column, a fixed strided split and a fixed tree, so the order never changes.
+__global__ void __launch_bounds__(256)
+k_col_sums(const double* __restrict__ part, int nblk, int ncol, double* __restrict__ sums) {
+  __shared__ double r1[256], r2[256];
+  const int c = blockIdx.x, t = threadIdx.x;
+  double v1 = 0.0, v2 = 0.0;
+  for (int b = t; b < nblk; b += 256) {
     v1 += part[((size_t)b * 2) * ncol + c];
     v2 += part[((size_t)b * 2 + 1) * ncol + c];
   }
+  r1[t] = v1;
+  r2[t] = v2;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+      r1[t] += r1[t + h];
+      r2[t] += r2[t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    sums[c] = r1[0];
+    sums[ncol + c] = r2[0];
+  }
+}
+
+__device__ inline void sum_parts(const double* sums, int ncol, int c, double& v1, double& v2) {
+  v1 = sums[c];
+  v2 = sums[ncol + c];
 }
 
 // After the initial dots (r.z, r.r): rz, bb = ||E_k||^2, every column active.
@@ -224,7 +253,7 @@ __global__ void k_scs_start(const double* __restrict__ part, int nblk, int ncol,
   const int c = threadIdx.x;
   if (c >= ncol) return;
   double rz, rr;
-  sum_parts(part, nblk, ncol, c, rz, rr);
+  sum_parts(part, ncol, c, rz, rr);
   sc[kRz * ncol + c] = rz;
   sc[kRr * ncol + c] = rr;
   sc[kBb * ncol + c] = rr;
@@ -241,7 +270,7 @@ __global__ void k_scs_alpha(const double* __restrict__ part, int nblk, int ncol,
   const int c = threadIdx.x;
   if (c >= ncol) return;
   double pq, unused;
-  sum_parts(part, nblk, ncol, c, pq, unused);
+  sum_parts(part, ncol, c, pq, unused);
   double al = 0.0;
   if (sc[kActive * ncol + c] != 0.0) {
     if (!(pq > 0.0) || !isfinite(pq)) {
@@ -281,7 +310,7 @@ __global__ void k_scs_beta(const double* __restrict__ part, int nblk, int ncol, 
   int act = 0;
   if (c < ncol) {
     double rz, rr;
-    sum_parts(part, nblk, ncol, c, rz, rr);
+    sum_parts(part, ncol, c, rz, rr);
     double be = 0.0;
     if (sc[kActive * ncol + c] != 0.0) {
       sc[kRr * ncol + c] = rr;
@@ -371,13 +400,14 @@ void launch_scs_dots(const ScsWork& w, const double* X, const double* Y, const d
   const int rows = 3 * w.n;
   const int per = (rows + w.nblk - 1) / w.nblk;
   k_col_dots<<<w.nblk, 256, 0, st>>>(X, Y, X2, Y2, rows, w.ncol, per, w.part);
+  k_col_sums<<<w.ncol, 256, 0, st>>>(w.part, w.nblk, w.ncol, w.sums);
 }
 
 void launch_scs_init(const ScsWork& w, hipStream_t st) {
   const size_t total = (size_t)w.n * 3 * w.ncol;
   k_scs_init<<<grid_for(total), 256, 0, st>>>(w.n, w.nq, w.ainv, w.x, w.r, w.z, w.p);
   launch_scs_dots(w, w.r, w.z, w.r, w.r, st);
-  k_scs_start<<<1, 128, 0, st>>>(w.part, w.nblk, w.ncol, w.sc, w.nact);
+  k_scs_start<<<1, 128, 0, st>>>(w.sums, w.nblk, w.ncol, w.sc, w.nact);
 }
 
 void launch_scs_iteration(const Geometry& g, const SysBuffers& b, const ScsWork& w, double tol,
@@ -385,11 +415,11 @@ void launch_scs_iteration(const Geometry& g, const SysBuffers& b, const ScsWork&
   const size_t total = (size_t)w.n * 3 * w.ncol;
   launch_scs_apply(g, b, w, w.p, w.q, st);
   launch_scs_dots(w, w.p, w.q, nullptr, nullptr, st);
-  k_scs_alpha<<<1, 128, 0, st>>>(w.part, w.nblk, w.ncol, w.sc, status);
+  k_scs_alpha<<<1, 128, 0, st>>>(w.sums, w.nblk, w.ncol, w.sc, status);
   k_scs_update<<<grid_for(total), 256, 0, st>>>(w.n, w.nq, w.ainv, w.sc, w.p, w.q, w.x, w.r,
                                                 w.z);
   launch_scs_dots(w, w.r, w.z, w.r, w.r, st);
-  k_scs_beta<<<1, 128, 0, st>>>(w.part, w.nblk, w.ncol, tol * tol, w.sc, w.nact);
+  k_scs_beta<<<1, 128, 0, st>>>(w.sums, w.nblk, w.ncol, tol * tol, w.sc, w.nact);
   k_scs_direction<<<grid_for(total), 256, 0, st>>>(total, w.ncol, w.sc, w.z, w.p);
 }
 
