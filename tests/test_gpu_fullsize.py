@@ -1,0 +1,87 @@
+"""Parity at the 24k-atom water box in the launch configuration that the benchmark times
+(mixed precision, 128 probes as one block of right-hand sides, K = 96, r_c = 9 A). The
+oracle evaluates sampled outputs one by one:
+
+- matvec: all 128 right-hand sides on the GPU. For two of them the oracle computes
+  l_i = Omega v_i + g_i (E_dir + E_rec + E_self)_i at 64 sampled atoms. The direct field
+  comes from a pair list restricted to those targets, the reciprocal field from the full
+  SPME of the oracle.
+- energy path: the Gauss quadrature value of probe 0 after the benchmark's 50 Lanczos
+  steps, against the oracle's single-probe run of 50 matvecs over the whole box.
+
+Tolerances as for the mixed path elsewhere: 2e-6 relative on the sampled matvec rows
+(norm over the sample), 1e-5 relative on the quadrature value."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import lanczos as olz
+from oracle import method as om
+from oracle import spme as osp
+from oracle import tensors as otz
+from oracle.exact import self_coefficient
+
+pytestmark = pytest.mark.gpu
+
+A = synth.ANGSTROM_BOHR
+
+
+@pytest.fixture(scope="module")
+def bench_case():
+    import paper_2307_02278_amd as P
+    wl = synth.workload("batched24k")
+    s = wl.systems[0]
+    K = tuple(wl.grid) * 3 if len(wl.grid) == 1 else tuple(wl.grid)
+    ds = P.DeviceSystem(s.pos, s.cell, s.alpha, s.omega, s.rvdw)
+    prm = P.Params(real_cutoff=wl.real_cutoff_angstrom * A, grid=K, n_probes=wl.n_probes,
+                   n_steps=wl.n_steps, block=wl.block, precision=P.PREC_MIXED,
+                   seed=wl.probe_seed)
+    plan = P.Plan([ds], prm)
+    return wl, s, K, plan
+
+
+def test_fullsize_matvec_sampled_rows(bench_case):
+    wl, s, K, plan = bench_case
+    inf = plan.info(0)
+    B = wl.block
+    g = torch.Generator().manual_seed(2024)
+    v = torch.randn(B, s.n, 3, dtype=torch.float64, generator=g)
+    got = plan.matvec(v.cuda()).cpu()
+    cols = [0, 77]
+    sample = np.sort(np.random.default_rng(5).choice(s.n, 64, replace=False))
+    pos = torch.as_tensor(s.pos, dtype=torch.float64)
+    gv = torch.as_tensor(s.omega * np.sqrt(s.alpha), dtype=torch.float64)
+    om2 = torch.as_tensor(s.omega ** 2, dtype=torch.float64)
+    rv = torch.as_tensor(s.rvdw, dtype=torch.float64)
+    y = v[cols].permute(1, 2, 0)                     # (N, 3, 2)
+    d = gv[:, None, None] * y
+    # direct field at the sampled targets
+    i, j, r = otz.pair_list(pos, s.cell, inf.r_pair, targets=sample)
+    rn = torch.sqrt((r * r).sum(-1))
+    Ad, Bd = otz.radial_direct(rn, inf.tau, 0.83 * (rv[i] + rv[j]), 6.0)
+    Edir = torch.zeros_like(d).index_add(0, i, otz.apply_pairs(Ad, Bd, r, d[j]))
+    # reciprocal field (whole grid) and self field
+    G = osp.influence(s.cell, list(K), inf.spline_order, inf.tau)
+    grid = osp.spread(pos, s.cell, list(K), inf.spline_order, d)
+    Erec = osp.gather(pos, s.cell, list(K), inf.spline_order, osp.convolve(grid, G))
+    E = Edir + Erec + self_coefficient(inf.tau) * d
+    want = om2[:, None, None] * y + gv[:, None, None] * E      # (N, 3, 2)
+    want = want[sample].permute(2, 0, 1)
+    have = got[cols][:, sample]
+    err = float((have - want).norm() / want.norm())
+    assert err < 2e-6, err
+
+
+def test_fullsize_quadrature_of_probe_zero(bench_case):
+    wl, s, K, plan = bench_case
+    e = plan.execute()
+    plan.check()
+    assert torch.isfinite(e).all()
+    q = plan.quadrature()
+    inf = plan.info(0)
+    op = om.Operator(s, om.MethodParams(tau=inf.tau, r_pair=inf.r_pair, grid=K,
+                                        order=inf.spline_order))
+    ref = olz.slq(op, s.n, s.omega, seed=wl.probe_seed, n_probes=1, m=wl.n_steps,
+                  reorth="none")
+    assert float(q[0]) == pytest.approx(float(ref.q[0]), rel=1e-5)
