@@ -10,7 +10,14 @@ oracle evaluates sampled outputs one by one:
   steps, against the oracle's single-probe run of 50 matvecs over the whole box.
 
 Tolerances as for the mixed path elsewhere: 2e-6 relative on the sampled matvec rows
-(norm over the sample), 1e-5 relative on the quadrature value."""
+(norm over the sample), 1e-5 relative on the quadrature value.
+
+The 12k-atom organic box in the forces leg's configuration (mixed, 64 probes x 40 steps
+as one block, K = 80, forces) gets the same sampled-row matvec check. Its forces are
+checked by a property that holds at any size: along the unit direction u = F / |F|, the
+central difference -(E(R + h u) - E(R - h u)) / 2h of the GPU energy at fixed probes
+equals |F|. h = 5e-3 bohr keeps the float32 rounding of the energy (about 1e-6 Ha)
+below 1e-4 of the difference; the bound is 2e-3."""
 import numpy as np
 import pytest
 import torch
@@ -41,14 +48,12 @@ def bench_case():
     return wl, s, K, plan
 
 
-def test_fullsize_matvec_sampled_rows(bench_case):
-    wl, s, K, plan = bench_case
+def _sampled_rows(s, K, plan, B):
     inf = plan.info(0)
-    B = wl.block
     g = torch.Generator().manual_seed(2024)
     v = torch.randn(B, s.n, 3, dtype=torch.float64, generator=g)
     got = plan.matvec(v.cuda()).cpu()
-    cols = [0, 77]
+    cols = [0, B - 13]
     sample = np.sort(np.random.default_rng(5).choice(s.n, 64, replace=False))
     pos = torch.as_tensor(s.pos, dtype=torch.float64)
     gv = torch.as_tensor(s.omega * np.sqrt(s.alpha), dtype=torch.float64)
@@ -69,7 +74,12 @@ def test_fullsize_matvec_sampled_rows(bench_case):
     want = om2[:, None, None] * y + gv[:, None, None] * E      # (N, 3, 2)
     want = want[sample].permute(2, 0, 1)
     have = got[cols][:, sample]
-    err = float((have - want).norm() / want.norm())
+    return float((have - want).norm() / want.norm())
+
+
+def test_fullsize_matvec_sampled_rows(bench_case):
+    wl, s, K, plan = bench_case
+    err = _sampled_rows(s, K, plan, wl.block)
     assert err < 2e-6, err
 
 
@@ -85,3 +95,40 @@ def test_fullsize_quadrature_of_probe_zero(bench_case):
     ref = olz.slq(op, s.n, s.omega, seed=wl.probe_seed, n_probes=1, m=wl.n_steps,
                   reorth="none")
     assert float(q[0]) == pytest.approx(float(ref.q[0]), rel=1e-5)
+
+
+@pytest.fixture(scope="module")
+def forces_case():
+    import paper_2307_02278_amd as P
+    wl = synth.workload("forces12k")
+    s = wl.systems[0]
+    K = tuple(wl.grid) * 3
+    ds = P.DeviceSystem(s.pos, s.cell, s.alpha, s.omega, s.rvdw)
+    prm = P.Params(real_cutoff=wl.real_cutoff_angstrom * A, grid=K, n_probes=wl.n_probes,
+                   n_steps=wl.n_steps, block=wl.block, precision=P.PREC_MIXED,
+                   seed=wl.probe_seed, want_forces=True)
+    return wl, s, K, P.Plan([ds], prm)
+
+
+def test_fullsize_forces_box_matvec_sampled_rows(forces_case):
+    wl, s, K, plan = forces_case
+    err = _sampled_rows(s, K, plan, wl.block)
+    assert err < 2e-6, err
+
+
+def test_fullsize_forces_match_directional_derivative(forces_case):
+    wl, s, K, plan = forces_case
+    pos = torch.as_tensor(s.pos, dtype=torch.float64, device="cuda")
+    plan.set_positions(pos)
+    _, f = plan.execute(forces=True)
+    plan.check()
+    fn = float(f.norm())
+    u = f / fn
+    h = 5e-3
+    es = []
+    for sgn in (1.0, -1.0):
+        plan.set_positions(pos + sgn * h * u)
+        es.append(float(plan.execute()[0]))
+        plan.check()
+    slope = -(es[0] - es[1]) / (2.0 * h)
+    assert slope == pytest.approx(fn, rel=2e-3), (slope, fn)
