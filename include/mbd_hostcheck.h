@@ -51,6 +51,10 @@ int32_t mbdh_tridiag_adjoint(const double* a, const double* b, int32_t n, double
  * rule behind the imaginary-frequency grid of mbd_scs. */
 void mbdh_gauss_legendre(int32_t n, double* x, double* w);
 
+/* Screening tensor of mbd_scs, T_SR = (1 - f) T_GG = A I - B r r^T, at squared distance r2,
+ * sigma_ij^2 = sig2, damping radius S = beta (R_i + R_j) and steepness d. */
+void mbdh_scs_kernel(double r2, double sig2, double S, double d, double* A, double* B);
+
 #ifdef __cplusplus
 }
 #endif

@@ -125,6 +125,8 @@ HOSTCHECK_SIGNATURES = [
      [C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
       C.POINTER(C.c_double)]),
     ("mbdh_gauss_legendre", None, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    ("mbdh_scs_kernel", None, [C.c_double, C.c_double, C.c_double, C.c_double,
+                               C.POINTER(C.c_double), C.POINTER(C.c_double)]),
 ]
 
 _lib = None

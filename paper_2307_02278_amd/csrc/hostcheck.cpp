@@ -64,4 +64,8 @@ int32_t mbdh_tridiag_adjoint(const double* a, const double* b, int32_t n, double
 
 void mbdh_gauss_legendre(int32_t n, double* x, double* w) { mbd::gauss_legendre(n, x, w); }
 
+void mbdh_scs_kernel(double r2, double sig2, double S, double d, double* A, double* B) {
+  mbd::scs_kernel(r2, sig2, S, d, *A, *B);
+}
+
 }  // extern "C"

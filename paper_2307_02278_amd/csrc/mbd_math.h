@@ -372,6 +372,30 @@ MBD_HD void tridiag_sqrt_adjoint(const double* theta, const double* u, int n, in
   }
 }
 
+// Screening tensor of the range-separated SCS, T_SR = (1 - f) T_GG = A I - B r r^T, at
+// squared distance r2 for a pair with sigma_ij^2 = sig2, damping radius S and steepness d:
+//   1 - f = 1 / (1 + exp(d (r / S - 1))),
+//   A = (1 - f) (erf z - c) / r^3,  B = (1 - f) (3 erf z - c (3 + 2 z^2)) / r^5,
+//   z^2 = r2 / sig2,  c = (2 / sqrt pi) z exp(-z^2).
+// Beyond r = 7 sigma_ij, erf z = 1 and c (3 + 2 z^2) < 1e-18, so the bare tensor is used
+// (identical in float64).
+MBD_HD void scs_kernel(double r2, double sig2, double S, double d, double& A, double& B) {
+  const double r = sqrt(r2);
+  const double omf = 1.0 / (1.0 + exp(d * (r / S - 1.0)));
+  const double z2 = r2 / sig2;
+  const double ir2 = 1.0 / r2;
+  const double ir3 = ir2 / r;
+  A = omf * ir3;
+  B = 3.0 * omf * ir3 * ir2;
+  if (z2 < 49.0) {
+    const double z = sqrt(z2);
+    const double c = 1.1283791670955126 * z * exp(-z2);
+    const double er = erf(z);
+    A = omf * (er - c) * ir3;
+    B = omf * (3.0 * er - c * (3.0 + 2.0 * z2)) * ir3 * ir2;
+  }
+}
+
 // Gauss-Legendre rule on [-1, 1]: the nodes are the roots of the Legendre polynomial
 // P_n, found by Newton's method from the asymptotic guesses cos(pi (i + 3/4) / (n + 1/2));
 // P_n and P_n' come from the three-term recurrence (j + 1) P_{j+1} = (2j + 1) x P_j - j P_{j-1}

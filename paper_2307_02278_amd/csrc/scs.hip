@@ -19,16 +19,13 @@
 #include <cmath>
 
 #include "common.h"
+#include "mbd_math.h"
 
 namespace mbd {
 namespace {
 
-constexpr double kTwoOverSqrtPi = 1.1283791670955126;
 // 1 - f = 1 / (1 + e^z) is below 1e-16 for z > 36.8: such pairs add nothing in float64
 constexpr double kDampSkip = 36.8;
-// Beyond r = 7 sigma_ij, erf(z) = 1 and c (3 + 2 z^2) < 1e-18 in float64: T_GG is the bare
-// tensor A = 1/r^3, B = 3/r^5 to the last bit.
-constexpr double kCloudFar2 = 49.0;
 
 // CG scalar rows of ScsWork::sc ([kScsRows][ncol])
 enum { kRz = 0, kPq = 1, kAlpha = 2, kBeta = 3, kRr = 4, kActive = 5, kBb = 6, kScsRows = 8 };
@@ -112,22 +109,10 @@ k_scs_apply(const Geometry geo, const int* __restrict__ cell_start,
           const double rz = locd[4 * j + 2] - zi + sz;
           const double r2 = rx * rx + ry * ry + rz * rz;
           if (r2 >= rp2) continue;
-          const double r = sqrt(r2);
-          const double zf = dd * (r / (Si + locd[4 * j + 3]) - 1.0);
-          if (zf > kDampSkip || !fv) continue;
-          const double omf = 1.0 / (1.0 + exp(zf));
-          const double z2 = r2 / (s2i + sig2[(size_t)j * nq + f]);
-          const double ir2 = 1.0 / r2;
-          const double ir3 = ir2 / r;
-          double A = omf * ir3, Bk = 3.0 * omf * ir3 * ir2;
-          if (z2 < kCloudFar2) {
-            // clouds still overlap: T_GG differs from the bare tensor
-            const double z = sqrt(z2);
-            const double c = kTwoOverSqrtPi * z * exp(-z2);
-            const double er = erf(z);
-            A = omf * (er - c) * ir3;
-            Bk = omf * (3.0 * er - c * (3.0 + 2.0 * z2)) * ir3 * ir2;
-          }
+          const double S = Si + locd[4 * j + 3];
+          if (dd * (sqrt(r2) / S - 1.0) > kDampSkip || !fv) continue;
+          double A, Bk;
+          scs_kernel(r2, s2i + sig2[(size_t)j * nq + f], S, dd, A, Bk);
           const double* pj = p + (size_t)j * 3 * ncol + 3 * f;
 #pragma unroll
           for (int k = 0; k < 3; ++k) {

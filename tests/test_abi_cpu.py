@@ -288,3 +288,19 @@ def test_hostcheck_tridiagonal_adjoint_matches_autograd(n):
     assert bb[0] == 0.0
     if n > 1:
         assert np.allclose(list(bb)[1:], grads[1].numpy(), rtol=1e-9, atol=1e-12)
+
+
+def test_hostcheck_scs_kernel_matches_oracle():
+    """The screening tensor of the GPU solver (host build of the same source) against the
+    oracle's (1 - f) T_GG, on both sides of the 7-sigma switch to the bare tensor."""
+    from oracle import scs as osc
+    h = L.hostcheck()
+    for r, sig2, S, d in [(2.0, 1.7, 5.0, 6.0), (4.5, 2.9, 5.4, 6.0), (9.0, 0.8, 5.8, 6.0),
+                          (16.0, 1.2, 6.2, 6.0), (3.1, 9.0, 4.0, 8.0)]:
+        A, B = C.c_double(), C.c_double()
+        h.mbdh_scs_kernel(r * r, sig2, S, d, C.byref(A), C.byref(B))
+        rt = torch.tensor(r, dtype=torch.float64)
+        Ag, Bg = osc.radial_gauss(rt, torch.tensor(sig2, dtype=torch.float64).sqrt())
+        g = float(otz.one_minus_fermi(rt, S, d))
+        assert A.value == pytest.approx(g * float(Ag), rel=1e-13)
+        assert B.value == pytest.approx(g * float(Bg), rel=1e-13)
