@@ -235,7 +235,8 @@ typedef struct {
  * rvdw_scs as the system's parameters. Errors: MBD_E_ARG (bad arguments),
  * MBD_E_NOT_POSDEF (p^T M p <= 0: the screening matrix is not positive definite at some
  * frequency), MBD_E_NOCONV (max_iter reached; outputs are written from the last iterate),
- * MBD_E_HIP, MBD_E_OOM. */
+ * MBD_E_HIP, MBD_E_OOM. The call resets the plan's device status word, so call mbd_check
+ * for an execute before calling mbd_scs. */
 mbd_status mbd_scs(mbd_plan plan, int32_t sys, const mbd_scs_params* prm, double* alpha_scs,
                    double* omega_scs, double* rvdw_scs, double* alpha_freq, mbd_scs_info* info);
 
