@@ -12,6 +12,11 @@ oracle evaluates sampled outputs one by one:
 Tolerances as for the mixed path elsewhere: 2e-6 relative on the sampled matvec rows
 (norm over the sample), 1e-5 relative on the quadrature value.
 
+The two small workloads run in their own full configurations (float64, one probe per
+block): the 96-atom fluid (8 probes x 30 steps) against the oracle's energy with all
+probes, and the 3000-atom water box (32 probes x 40 steps) against the oracle's
+quadrature of probes 0 and 31 (bound 1e-9 relative in float64).
+
 The 12k-atom organic box in the forces leg's configuration (mixed, 64 probes x 40 steps
 as one block, K = 80, forces) gets the same sampled-row matvec check. Its forces are
 checked by a property that holds at any size: along the unit direction u = F / |F|, the
@@ -132,3 +137,44 @@ def test_fullsize_forces_match_directional_derivative(forces_case):
         plan.check()
     slope = -(es[0] - es[1]) / (2.0 * h)
     assert slope == pytest.approx(fn, rel=2e-3), (slope, fn)
+
+
+def _workload_plan(wl):
+    import paper_2307_02278_amd as P
+    s = wl.systems[0]
+    K = tuple(wl.grid) * 3
+    ds = P.DeviceSystem(s.pos, s.cell, s.alpha, s.omega, s.rvdw)
+    tau = wl.tau_inv_angstrom * synth.BOHR_ANGSTROM if wl.tau_inv_angstrom else 0.0
+    prm = P.Params(ewald_tau=tau, real_cutoff=wl.real_cutoff_angstrom * A, grid=K,
+                   n_probes=wl.n_probes, n_steps=wl.n_steps, block=wl.block,
+                   precision=P.PREC_FP64, seed=wl.probe_seed)
+    return s, K, P.Plan([ds], prm)
+
+
+def test_tiny_workload_energy_all_probes():
+    wl = synth.workload("tiny")
+    s, K, plan = _workload_plan(wl)
+    e = float(plan.execute()[0])
+    plan.check()
+    inf = plan.info(0)
+    op = om.Operator(s, om.MethodParams(tau=inf.tau, r_pair=inf.r_pair, grid=K,
+                                        order=inf.spline_order))
+    ref = olz.slq(op, s.n, s.omega, seed=wl.probe_seed, n_probes=wl.n_probes, m=wl.n_steps,
+                  reorth="none")
+    assert e == pytest.approx(float(ref.energy), rel=1e-9)
+
+
+def test_medium_workload_quadrature_of_two_probes():
+    wl = synth.workload("medium")
+    s, K, plan = _workload_plan(wl)
+    e = plan.execute()
+    plan.check()
+    assert torch.isfinite(e).all()
+    q = plan.quadrature()
+    inf = plan.info(0)
+    op = om.Operator(s, om.MethodParams(tau=inf.tau, r_pair=inf.r_pair, grid=K,
+                                        order=inf.spline_order))
+    for l in (0, wl.n_probes - 1):
+        ref = olz.slq(op, s.n, s.omega, seed=wl.probe_seed, n_probes=1, m=wl.n_steps,
+                      reorth="none", probes=[l])
+        assert float(q[l]) == pytest.approx(float(ref.q[0]), rel=1e-9), l
