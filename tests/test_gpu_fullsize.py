@@ -17,6 +17,10 @@ block): the 96-atom fluid (8 probes x 30 steps) against the oracle's energy with
 probes, and the 3000-atom water box (32 probes x 40 steps) against the oracle's
 quadrature of probes 0 and 31 (bound 1e-9 relative in float64).
 
+The uneven batch (32 water boxes of 500 to 20 000 atoms in one plan, mixed, 64 probes x
+40 steps, forces) gets the sampled-row check on its largest, smallest and a middle
+system, and the directional-derivative check of the forces on its smallest system.
+
 The 12k-atom organic box in the forces leg's configuration (mixed, 64 probes x 40 steps
 as one block, K = 80, forces) gets the same sampled-row matvec check. Its forces are
 checked by a property that holds at any size: along the unit direction u = F / |F|, the
@@ -53,13 +57,13 @@ def bench_case():
     return wl, s, K, plan
 
 
-def _sampled_rows(s, K, plan, B):
-    inf = plan.info(0)
+def _sampled_rows(s, K, plan, B, sys=0):
+    inf = plan.info(sys)
     g = torch.Generator().manual_seed(2024)
     v = torch.randn(B, s.n, 3, dtype=torch.float64, generator=g)
-    got = plan.matvec(v.cuda()).cpu()
+    got = plan.matvec(v.cuda(), sys=sys).cpu()
     cols = [0, B - 13]
-    sample = np.sort(np.random.default_rng(5).choice(s.n, 64, replace=False))
+    sample = np.sort(np.random.default_rng(5).choice(s.n, min(64, s.n), replace=False))
     pos = torch.as_tensor(s.pos, dtype=torch.float64)
     gv = torch.as_tensor(s.omega * np.sqrt(s.alpha), dtype=torch.float64)
     om2 = torch.as_tensor(s.omega ** 2, dtype=torch.float64)
@@ -178,3 +182,46 @@ def test_medium_workload_quadrature_of_two_probes():
         ref = olz.slq(op, s.n, s.omega, seed=wl.probe_seed, n_probes=1, m=wl.n_steps,
                       reorth="none", probes=[l])
         assert float(q[l]) == pytest.approx(float(ref.q[0]), rel=1e-9), l
+
+
+@pytest.fixture(scope="module")
+def uneven_case():
+    import paper_2307_02278_amd as P
+    wl = synth.workload("uneven")
+    ds = [P.DeviceSystem(x.pos, x.cell, x.alpha, x.omega, x.rvdw) for x in wl.systems]
+    prm = P.Params(real_cutoff=wl.real_cutoff_angstrom * A, grid=(0, 0, 0),
+                   n_probes=wl.n_probes, n_steps=wl.n_steps, block=wl.block,
+                   precision=P.PREC_MIXED, seed=wl.probe_seed, want_forces=True)
+    return wl, ds, P.Plan(ds, prm)
+
+
+def test_uneven_batch_sampled_rows(uneven_case):
+    wl, ds, plan = uneven_case
+    sizes = [x.n for x in wl.systems]
+    order = np.argsort(sizes)
+    for k in (int(order[-1]), int(order[0]), int(order[len(order) // 2])):
+        K = tuple(plan.info(k).grid)
+        err = _sampled_rows(wl.systems[k], K, plan, wl.block, sys=k)
+        assert err < 2e-6, (k, err)
+
+
+def test_uneven_batch_forces_match_directional_derivative(uneven_case):
+    wl, ds, plan = uneven_case
+    k = int(np.argmin([x.n for x in wl.systems]))
+    lo = sum(x.n for x in wl.systems[:k])
+    n = wl.systems[k].n
+    _, f = plan.execute(forces=True)
+    plan.check()
+    fk = f[lo:lo + n]
+    fn = float(fk.norm())
+    u = fk / fn
+    h = 5e-3
+    pos = ds[k].pos.clone()
+    es = []
+    for sgn in (1.0, -1.0):
+        plan.set_positions(pos + sgn * h * u, k)
+        es.append(float(plan.execute()[k]))
+        plan.check()
+    plan.set_positions(pos, k)
+    slope = -(es[0] - es[1]) / (2.0 * h)
+    assert slope == pytest.approx(fn, rel=2e-3), (slope, fn)
