@@ -329,37 +329,35 @@ def main():
         torch.cuda.synchronize()
         plan.check()
         log(f"warmup {w}: E = {float(e[0]):.10e} Ha")
-    plan.stage_times()
-    plan.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        e = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    plan.set_timing(False)
+    def timed(n):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(n):
+            out = step()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, out
+
+    # The timed steps: execute replayed from its captured HIP graph (the plan's
+    # production mode), or launched eagerly with --eager.
+    dt, e = timed(args.steps)
     plan.check()
-    stages = plan.stage_times()
-    dt = t1 - t0
     energy = float(e[0])
     ms_per_step = 1000.0 * dt / args.steps
     value = R * m * args.steps / dt
-    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.1f} matvecs/s, "
-        f"E = {energy:.10e}")
-    graph_rate = None
-    if not args.eager:
-        # the same steps with execute replayed from its captured HIP graph
-        step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(args.steps):
-            eg = step()
-        torch.cuda.synchronize()
-        tg = time.perf_counter() - t0
-        plan.check()
-        assert float(eg[0]) == energy
-        graph_rate = R * m * args.steps / tg
-        log(f"graph replay: {1000 * tg / args.steps:.2f} ms/step, {graph_rate:.1f} matvecs/s")
+    log(f"timed {args.steps} steps ({'eager' if args.eager else 'graph replay'}): "
+        f"{ms_per_step:.2f} ms/step, {value:.1f} matvecs/s, E = {energy:.10e}")
+    # The same steps once more, launched eagerly with HIP events around every stage
+    # (per-stage times and the dominant kernel's roofline; not part of the value).
+    plan.stage_times()
+    plan.set_timing(True)
+    te, ee = timed(args.steps)
+    plan.set_timing(False)
+    plan.check()
+    stages = plan.stage_times()
+    assert float(ee[0]) == energy
+    eager_rate = R * m * args.steps / te
+    log(f"eager with stage events: {1000 * te / args.steps:.2f} ms/step, "
+        f"{eager_rate:.1f} matvecs/s")
 
     # Per-stage averages and the dominant kernel's roofline.
     stage_ms = {k: v[0] / args.steps for k, v in stages.items() if v[1] > 0}
@@ -452,7 +450,8 @@ def main():
                                "128 probes x 50 Lanczos steps as one RHS block",
                    "n_atoms": s.n, "grid": list(K), "probes": R, "lanczos_steps": m,
                    "block": B, "pairs": n_pairs},
-        "graph_matvecs_per_s": round(graph_rate, 1) if graph_rate else None,
+        "execution": "eager" if args.eager else "hip_graph_replay",
+        "eager_stage_timed_matvecs_per_s": round(eager_rate, 1),
         "energy_ms": round(ms_per_step, 3),
         "energy_ha": energy,
         "plain_matvecs_per_s": round(plain_rate, 2) if plain_rate else None,
