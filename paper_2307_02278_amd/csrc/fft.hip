@@ -495,6 +495,92 @@ k_fft_reg(float* __restrict__ grid, GridDims gd, const float* __restrict__ G) {
   }
 }
 
+// x passes with one lane per column (K even, M = K/2). A real line of K points is packed
+// as M complex points z[n] = x[2n] + i x[2n+1] and transformed with one M-point FFT:
+//   forward:  X[k] = (Z[k] + conj Z[M-k]) / 2 + W_K^k (Z[k] - conj Z[M-k]) / 2i,
+//             k = 0..M, with Z[M] = Z[0];
+//   inverse:  Z'[k] = A[k] + i B[k],  A[k] = X[k] + conj X[M-k],
+//             B[k] = (X[k] - conj X[M-k]) W_K^{-k},  then z = inverse M-point FFT of Z',
+//             x[2n] = Re z[n], x[2n+1] = Im z[n].
+// The imaginary parts of X[0] and X[M] are taken as zero, as in the real part of a full
+// inverse transform. A wavefront covers 64 consecutive columns, so every load and store
+// is one contiguous 256-byte row; no lane exchange is needed.
+template <int K, bool FWD>
+__global__ void __launch_bounds__(64)
+k_fft_x_real(float* __restrict__ grid, GridDims gd) {
+  constexpr int M = K / 2;
+  constexpr TwTable<K> T{};
+  float* g = grid + (size_t)(blockIdx.y + gd.chunk0) * gd.chunk_elems;
+  const long col = (long)blockIdx.x * 64 + threadIdx.x;
+  const int BG = gd.BG;
+  const int b = (int)(col % BG);
+  const long line = col / BG;
+  if (line >= (long)gd.K2 * gd.K3) return;
+  const size_t base = (size_t)line * gd.XS * BG + b;
+  const size_t wbase = (size_t)__builtin_amdgcn_readfirstlane((unsigned)(base >> 32)) << 32 |
+                       (size_t)(unsigned)__builtin_amdgcn_readfirstlane((unsigned)base);
+  float* gw = g + wbase;
+  const uint32_t lo = (uint32_t)(base - wbase);
+  const uint32_t stride = (uint32_t)BG;
+  float zr[M], zi[M];
+#pragma unroll
+  for (int n = 0; n < M; ++n) {
+    zr[n] = at(gw, lo + (uint32_t)(2 * n) * stride);
+    zi[n] = at(gw, lo + (uint32_t)(2 * n + 1) * stride);
+  }
+  // an opaque copy of the lane offset for the stores: otherwise the compiler keeps the
+  // load addresses live through the transform to reuse them
+  uint32_t lo_st = lo;
+  if constexpr (FWD) {
+    reg_stages<M, 0, true>(zr, zi);
+    asm volatile("" : "+v"(lo_st));
+    at(gw, lo_st) = zr[0] + zi[0];
+    at(gw, lo_st + stride) = 0.f;
+    at(gw, lo_st + (uint32_t)(2 * M) * stride) = zr[0] - zi[0];
+    at(gw, lo_st + (uint32_t)(2 * M + 1) * stride) = 0.f;
+#pragma unroll
+    for (int k = 1; k < M; ++k) {
+      const float fer = 0.5f * (zr[k] + zr[M - k]), fei = 0.5f * (zi[k] - zi[M - k]);
+      const float forr = 0.5f * (zi[k] + zi[M - k]), foi = -0.5f * (zr[k] - zr[M - k]);
+      // W_K^k = cos - i sin
+      const float wr = T.c[k] * forr + T.s[k] * foi, wi = T.c[k] * foi - T.s[k] * forr;
+      at(gw, lo_st + (uint32_t)(2 * k) * stride) = fer + wr;
+      at(gw, lo_st + (uint32_t)(2 * k + 1) * stride) = fei + wi;
+    }
+  } else {
+    // zr, zi hold X[0..M); X[M] is the last complex pair of the half spectrum
+    const float xmr = at(gw, lo + (uint32_t)(2 * M) * stride);
+    const float x0r = zr[0];
+    zr[0] = x0r + xmr;
+    zi[0] = x0r - xmr;
+#pragma unroll
+    for (int k = 1; k <= M / 2; ++k) {
+      const int m = M - k;
+      const float ar = zr[k], ai = zi[k], br = zr[m], bi = zi[m];
+      {
+        // index k: a = X[k], b = X[M-k]; twiddle W_K^{-k} = cos + i sin
+        const float Ar = ar + br, Ai = ai - bi, Dr = ar - br, Di = ai + bi;
+        const float Br = Dr * T.c[k] - Di * T.s[k], Bi = Dr * T.s[k] + Di * T.c[k];
+        zr[k] = Ar - Bi;
+        zi[k] = Ai + Br;
+      }
+      if (m != k) {
+        const float Ar = br + ar, Ai = bi - ai, Dr = br - ar, Di = bi + ai;
+        const float Br = Dr * T.c[m] - Di * T.s[m], Bi = Dr * T.s[m] + Di * T.c[m];
+        zr[m] = Ar - Bi;
+        zi[m] = Ai + Br;
+      }
+    }
+    reg_stages<M, 0, false>(zr, zi);
+    asm volatile("" : "+v"(lo_st));
+#pragma unroll
+    for (int n = 0; n < M; ++n) {
+      at(gw, lo_st + (uint32_t)(2 * n) * stride) = zr[n];
+      at(gw, lo_st + (uint32_t)(2 * n + 1) * stride) = zi[n];
+    }
+  }
+}
+
 #define MBD_REG_SIZES(X) \
   X(8) X(10) X(12) X(16) X(18) X(20) X(24) X(30) X(32) X(36) X(40) X(48) X(50) X(54) \
   X(60) X(64) X(72) X(80) X(90) X(96) X(100) X(108) X(120) X(128)
@@ -518,6 +604,19 @@ void launch_pass(int K, R* grid, const GridDims& gd, int nchunks, const R* twc, 
   const long cols = nlines * gd.BG;
   if constexpr (sizeof(R) == 4) {
     if (gd.BG >= 16) {
+      if constexpr (MODE == kXFwd || MODE == kXInv) {
+        dim3 g1((unsigned)((cols + 63) / 64), nchunks);
+        switch (K) {
+#define MBD_REGX(KK)                                                                    \
+          case KK:                                                                      \
+            k_fft_x_real<KK, MODE == kXFwd><<<g1, 64, 0, st>>>((float*)grid, gd);       \
+            return;
+          MBD_REG_SIZES(MBD_REGX)
+#undef MBD_REGX
+          default:
+            break;
+        }
+      }
       dim3 g2((unsigned)((cols + 31) / 32), nchunks);
       switch (K) {
 #define MBD_REG(KK)                                                                    \
