@@ -136,6 +136,25 @@ def test_matvec_noncubic_grid_radix_3_5():
     assert _rel(plan.matvec(v.cuda()).cpu(), op(v.permute(1, 2, 0)).permute(2, 0, 1)) < 1e-11
 
 
+@pytest.mark.parametrize("grid", [(18, 24, 30), (30, 20, 24)])
+@pytest.mark.parametrize("comp", [4, 15])
+def test_matvec_mixed_noncubic_odd_half_lengths(grid, comp):
+    """Float32 grid path with 16 right-hand sides on unequal axes whose x length K1 = 18 or
+    30 packs into an odd number (9, 15) of complex points in the real-column x passes;
+    the reciprocal part alone (comp 4) isolates the transforms."""
+    import paper_2307_02278_amd as P
+    base = synth.tiny_random(seed=7, n=60)
+    cell = np.diag([10.0, 11.5, 13.0]) * A
+    pos = base.pos * np.array([1.0, 1.15, 1.3])
+    s = synth.System("ortho", pos, cell, base.alpha[:60], base.omega[:60], base.rvdw[:60])
+    plan, _ = _plan(s, P.PREC_MIXED, 16, grid=grid, tau_ang=0.35, rc_ang=13.0)
+    op = _oracle_op(s, plan)
+    v = torch.randn(16, s.n, 3, dtype=torch.float64, generator=torch.Generator().manual_seed(5))
+    got = plan.matvec(v.cuda(), components=comp).cpu()
+    want = op(v.permute(1, 2, 0), comp).permute(2, 0, 1)
+    assert _rel(got, want) < (2e-6 if comp == 15 else 1e-5)
+
+
 def _compare_lanczos(s, prec, block, R, m, tol_q, tol_e, **kw):
     import paper_2307_02278_amd as P
     plan, _ = _plan(s, prec, block, R=R, m=m, **kw)
