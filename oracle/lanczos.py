@@ -56,8 +56,9 @@ def lanczos(matvec: Callable, v: torch.Tensor, m: int, reorth: str = "full",
             for _ in range(2):
                 w = w - Ym.T @ (Ym @ w)
         bn = torch.linalg.norm(w)
-        scale = max(abs(float(a)), float(b_prev) if b_prev is not None else 0.0)
-        if float(bn) <= breakdown * scale:
+        scale = max(abs(float(a.detach())),
+                    float(b_prev.detach()) if b_prev is not None else 0.0)
+        if float(bn.detach()) <= breakdown * scale:
             break
         b_list.append(bn)
         b_prev = bn
@@ -104,7 +105,7 @@ def slq(op: Callable, n_atoms: int, omega, seed: int, n_probes: int, m: int,
     for l in range(len(probes)):
         res = lanczos(op, V[l], m, reorth=reorth)
         q, theta, _ = quadrature(res.a, res.b)
-        tmin = min(tmin, float(theta.min()))
+        tmin = min(tmin, float(theta.detach().min()))
         qs.append(q)
         As.append(res.a)
         Bs.append(res.b)

@@ -321,6 +321,36 @@ def diamond_box(n_cells: int = 4, a_ang: float = 3.567) -> System:
                   np.full(n, 0.45), np.full(n, 3.59))
 
 
+# A skewed right-handed cell (rows a1, a2, a3 in Angstrom) for the general-cell cases.
+SKEWED_CELL_ANGSTROM = np.array([[10.0, 0.0, 0.0], [2.6, 9.4, 0.0], [-1.7, 2.1, 10.8]])
+
+
+def triclinic_random(n: int = 80, seed: int = 3, dmin_ang: float = 1.6,
+                     cell_ang: Optional[np.ndarray] = None) -> System:
+    """Random atoms in a triclinic cell (default: SKEWED_CELL_ANGSTROM) with a minimum
+    periodic-image distance dmin, by rejection on uniform fractional coordinates;
+    alpha ~ U[5, 15], omega ~ U[0.3, 0.7], R_vdW ~ U[3, 4] as in the dense fluid."""
+    cell = SKEWED_CELL_ANGSTROM if cell_ang is None else np.asarray(cell_ang, float)
+    rng = np.random.default_rng(seed)
+    shifts = np.array([[i, j, k] for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)])
+    pts = []
+    while len(pts) < n:
+        f = rng.uniform(0.0, 1.0, 3)
+        ok = True
+        for q in pts:
+            d = (f - q)[None, :] + shifts
+            if np.min(np.linalg.norm(d @ cell, axis=1)) < dmin_ang:
+                ok = False
+                break
+        if ok:
+            pts.append(f)
+    pos = np.array(pts) @ cell
+    alpha = rng.uniform(5.0, 15.0, n)
+    omega = rng.uniform(0.3, 0.7, n)
+    rvdw = rng.uniform(3.0, 4.0, n)
+    return System("triclinic", pos * ANGSTROM_BOHR, cell * ANGSTROM_BOHR, alpha, omega, rvdw)
+
+
 def workload(name: str) -> Workload:
     """The five synthetic workloads (tiny, medium, batched 24k, forces 12k, uneven).
 

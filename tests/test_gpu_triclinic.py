@@ -1,7 +1,6 @@
 """General (triclinic) cells on the GPU against the oracle, which evaluates the same
 SPME definition with reciprocal vectors and the direct sum over all images within
 the cutoff. Same tolerances as the orthorhombic parity and force tests."""
-import numpy as np
 import pytest
 import torch
 
@@ -15,32 +14,9 @@ A = synth.ANGSTROM_BOHR
 SEED = 12345
 
 
-def _triclinic_system(n=80, seed=3, dmin=1.6):
-    """Random atoms in a skewed cell, minimum image distance dmin (Angstrom)."""
-    cell = np.array([[10.0, 0.0, 0.0], [2.6, 9.4, 0.0], [-1.7, 2.1, 10.8]])
-    rng = np.random.default_rng(seed)
-    shifts = np.array([[i, j, k] for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)])
-    pts = []
-    while len(pts) < n:
-        f = rng.uniform(0.0, 1.0, 3)
-        ok = True
-        for q in pts:
-            d = (f - q)[None, :] + shifts
-            if np.min(np.linalg.norm(d @ cell, axis=1)) < dmin:
-                ok = False
-                break
-        if ok:
-            pts.append(f)
-    pos = np.array(pts) @ cell
-    alpha = rng.uniform(5.0, 15.0, n)
-    omega = rng.uniform(0.3, 0.7, n)
-    rvdw = rng.uniform(3.0, 4.0, n)
-    return synth.System("triclinic", pos * A, cell * A, alpha, omega, rvdw)
-
-
 @pytest.fixture(scope="module")
 def tri():
-    return _triclinic_system()
+    return synth.triclinic_random()
 
 
 def _plan(s, prec, block, R=4, m=10, forces=False):
