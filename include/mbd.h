@@ -79,6 +79,32 @@ typedef struct {
   const double* r_vdw;  /* device [N], van der Waals radius > 0, bohr                   */
 } mbd_system;
 
+/* Launch shape of one system's matvec. It changes how the work is laid out on the GPU:
+ * pair_wg_per_cu, pair_subsets and overlap leave every result bit unchanged; grid_chunk
+ * changes the summation order inside the spread and the gather, so results agree to
+ * rounding across chunk widths. A plan is bitwise reproducible for its shape. */
+typedef struct {
+  int32_t pair_wg_per_cu; /* work-groups per compute unit of the direct-space list kernel;
+                             0 => one work-group per 16-atom target group (all resident)  */
+  int32_t pair_subsets;   /* target subsets per list-kernel wavefront: 1, 2 or 4 (at least
+                             64 / block); 0 => the size rule (4096 wavefronts or more)    */
+  int32_t grid_chunk;     /* right-hand sides per SPME grid chunk: a power of two <= 64
+                             that divides block; 0 => 64 (mixed) or 16 (float64)         */
+  int32_t overlap;        /* pair kernel on a side stream, concurrent with the grid stages
+                             (single-system plans): 1 => forked before the spreads, 2 =>
+                             forked after them (beside the transforms only); 0 => one
+                             stream                                                       */
+} mbd_shape;
+
+enum {
+  MBD_TUNE_OFF = 0,       /* built-in shape: pair_wg_per_cu 0, size rule, default chunk,
+                             overlap 1                                                    */
+  MBD_TUNE_MEASURE = 1,   /* time candidate shapes on each system at plan creation and
+                             keep the fastest (reused from tune_cache when it holds one)  */
+  MBD_TUNE_GIVEN = 2      /* use params.shape as given, for every system                 */
+};
+enum { MBD_SHAPE_BUILTIN = 0, MBD_SHAPE_MEASURED = 1, MBD_SHAPE_CACHED = 2, MBD_SHAPE_GIVEN = 3 };
+
 typedef struct {
   double damp_beta;     /* range parameter beta of the Fermi damping (> 0), e.g. 0.83   */
   double damp_d;        /* steepness d of the Fermi damping (> 0), e.g. 6               */
@@ -118,6 +144,12 @@ typedef struct {
                            Q_l = [R_0^T E_1^T sqrt(T) E_1 R_0]_ll with T the block
                            tridiagonal of the A_k and B_k; the same m matvecs per probe span
                            a Krylov space krylov_block times wider per block.             */
+  int32_t tune;         /* MBD_TUNE_OFF / MBD_TUNE_MEASURE / MBD_TUNE_GIVEN               */
+  mbd_shape shape;      /* the shape for MBD_TUNE_GIVEN (ignored otherwise)               */
+  const char* tune_cache;/* MBD_TUNE_MEASURE: path of a JSON-lines file of measured shapes,
+                           one object per line keyed by device architecture, N, grid,
+                           block, precision and forces; read at plan creation and
+                           appended with each new measurement. NULL => no file.         */
 } mbd_params;
 
 /* Values derived on the host for one system of a plan. */
@@ -130,6 +162,9 @@ typedef struct {
   int32_t block;        /* right-hand sides per block                                  */
   size_t workspace_bytes;
   int64_t n_pairs;      /* directed (i, j, image) pairs within r_pair at the current positions */
+  mbd_shape shape;      /* launch shape in use for this system                         */
+  int32_t shape_source; /* MBD_SHAPE_BUILTIN / MEASURED / CACHED / GIVEN                */
+  double tune_ms;       /* time of one measured matvec with that shape (0 if not measured) */
 } mbd_info;
 
 /* Probe definition (eq. dds): entry (l, i, a) of system s is +-1/sqrt(3N), the sign
@@ -159,7 +194,8 @@ mbd_status mbd_plan_info(mbd_plan plan, int32_t sys, mbd_info* info);
 mbd_status mbd_set_positions(mbd_plan plan, int32_t sys, const double* pos);
 
 /* Run Algorithm 1 for every system: R probes in blocks of `block` RHS, m Lanczos steps
- * each, Gauss quadrature per probe, then E = 1/2 (3N/R) sum_l Q_l - 3/2 sum omega.
+ * each, Gauss quadrature per probe, then E = 1/2 (3N/R) sum_l Q_l - 3/2 sum omega
+ * (eqs. hutch, sl4, plasmonic2).
  * energy: device [n_sys] float64.
  * forces: NULL, or device [sum of N][3] float64 (systems concatenated, caller atom order)
  *   receiving F = -dE/dR, the exact derivative of the fixed-probe estimator above with
@@ -167,8 +203,14 @@ mbd_status mbd_set_positions(mbd_plan plan, int32_t sys, const double* pos);
  *   reverse mode through the Lanczos recurrence and the quadrature, with one adjoint
  *   matvec and the bilinear pair and reciprocal force terms per step). Re-orthogonalization
  *   corrections are not differentiated (exact for MBD_REORTH_NONE). Requires a plan
- *   created with want_forces = 1, else MBD_E_STATE. */
-mbd_status mbd_execute(mbd_plan plan, double* energy, double* forces);
+ *   created with want_forces = 1, else MBD_E_STATE.
+ * energy_sd: NULL, or device [n_sys] float64 receiving the standard deviation of the
+ *   energy estimate from the spread of the per-probe quadrature values (the Hutchinson
+ *   trace estimator of eq. hutch is an average of R independent samples):
+ *   sd(E) = 1/2 (3N) s_Q / sqrt(R),  s_Q^2 = sum_l (Q_l - mean Q)^2 / (R - 1);
+ *   NaN when R = 1 (no spread to measure; not flagged as an error).
+ * The energy, the forces and energy_sd are reduced on the device in a fixed order. */
+mbd_status mbd_execute(mbd_plan plan, double* energy, double* forces, double* energy_sd);
 
 /* Synchronize the plan's stream and return the first device-detected error
  * (MBD_E_NOT_POSDEF, MBD_E_NONFINITE) since the last execute, else MBD_OK. */

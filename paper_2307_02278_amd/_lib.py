@@ -29,6 +29,19 @@ class MbdSystem(C.Structure):
     ]
 
 
+class MbdShape(C.Structure):
+    _fields_ = [
+        ("pair_wg_per_cu", C.c_int32),
+        ("pair_subsets", C.c_int32),
+        ("grid_chunk", C.c_int32),
+        ("overlap", C.c_int32),
+    ]
+
+
+TUNE_OFF, TUNE_MEASURE, TUNE_GIVEN = 0, 1, 2
+SHAPE_SOURCES = ["builtin", "measured", "cached", "given"]
+
+
 class MbdParams(C.Structure):
     _fields_ = [
         ("damp_beta", C.c_double),
@@ -49,6 +62,9 @@ class MbdParams(C.Structure):
         ("replica_cutoff", C.c_double),
         ("graph", C.c_int32),
         ("krylov_block", C.c_int32),
+        ("tune", C.c_int32),
+        ("shape", MbdShape),
+        ("tune_cache", C.c_char_p),
     ]
 
 
@@ -62,6 +78,9 @@ class MbdInfo(C.Structure):
         ("block", C.c_int32),
         ("workspace_bytes", C.c_size_t),
         ("n_pairs", C.c_int64),
+        ("shape", MbdShape),
+        ("shape_source", C.c_int32),
+        ("tune_ms", C.c_double),
     ]
 
 
@@ -87,7 +106,7 @@ SIGNATURES = [
      [C.POINTER(C.c_void_p), C.POINTER(MbdSystem), C.c_int32, C.POINTER(MbdParams), C.c_void_p]),
     ("mbd_plan_info", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(MbdInfo)]),
     ("mbd_set_positions", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
-    ("mbd_execute", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("mbd_execute", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("mbd_check", C.c_int32, [C.c_void_p]),
     ("mbd_matvec", C.c_int32,
      [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_uint32]),

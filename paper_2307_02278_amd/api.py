@@ -30,6 +30,9 @@ class Params:
     graph: bool = False             # replay execute from a captured HIP graph
     replica_cutoff: float = 0.0     # bohr; > 0 => replica method (float64, energy only)
     krylov_block: int = 1           # > 1 => block Lanczos over blocks of this many probes
+    tune: int = L.TUNE_OFF          # TUNE_OFF / TUNE_MEASURE / TUNE_GIVEN
+    shape: Optional[dict] = None    # TUNE_GIVEN: pair_wg_per_cu, pair_subsets, grid_chunk, overlap
+    tune_cache: Optional[str] = None  # TUNE_MEASURE: JSON-lines cache file
 
     def to_c(self) -> L.MbdParams:
         p = L.MbdParams()
@@ -53,6 +56,11 @@ class Params:
         p.graph = 1 if self.graph else 0
         p.replica_cutoff = self.replica_cutoff
         p.krylov_block = self.krylov_block
+        p.tune = self.tune
+        for k, v in (self.shape or {}).items():
+            setattr(p.shape, k, int(v))
+        self._cache_bytes = self.tune_cache.encode() if self.tune_cache else None
+        p.tune_cache = self._cache_bytes
         return p
 
 
@@ -103,16 +111,20 @@ class Plan:
         L.check(self.lib.mbd_plan_info(self.handle, sys, C.byref(inf)))
         return inf
 
-    def execute(self, forces: bool = False):
-        """E_MBD per system; with forces=True also F = -dE/dR, [sum N, 3] (float64, GPU)."""
+    def execute(self, forces: bool = False, energy_sd: bool = False):
+        """E_MBD per system; with forces=True also F = -dE/dR, [sum N, 3]; with
+        energy_sd=True also the standard deviation of each energy estimate (all float64,
+        on the GPU). Returns e, or a tuple (e[, f][, sd]) in that order."""
         e = torch.zeros(len(self.systems), dtype=torch.float64, device="cuda")
-        if not forces:
-            L.check(self.lib.mbd_execute(self.handle, C.c_void_p(e.data_ptr()), None))
+        f = (torch.zeros(sum(s.n for s in self.systems), 3, dtype=torch.float64, device="cuda")
+             if forces else None)
+        sd = torch.zeros(len(self.systems), dtype=torch.float64, device="cuda") if energy_sd \
+            else None
+        ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())
+        L.check(self.lib.mbd_execute(self.handle, ptr(e), ptr(f), ptr(sd)))
+        if not forces and not energy_sd:
             return e
-        f = torch.zeros(sum(s.n for s in self.systems), 3, dtype=torch.float64, device="cuda")
-        L.check(self.lib.mbd_execute(self.handle, C.c_void_p(e.data_ptr()),
-                                     C.c_void_p(f.data_ptr())))
-        return e, f
+        return tuple(x for x in (e, f, sd) if x is not None)
 
     def check(self):
         L.check(self.lib.mbd_check(self.handle))
@@ -170,10 +182,10 @@ class Plan:
         af = torch.empty(n_freq, n, dtype=torch.float64, device="cuda") if with_freq else None
         prm = L.MbdScsParams(n_freq, freq_scale, tol, max_iter)
         inf = L.MbdScsInfo()
-        L.check(self.lib.mbd_scs(self.handle, sys, C.byref(prm), C.c_void_p(out[0].data_ptr()),
-                                 C.c_void_p(out[1].data_ptr()), C.c_void_p(out[2].data_ptr()),
-                                 C.c_void_p(af.data_ptr()) if with_freq else None,
-                                 C.byref(inf)))
+        fn = self.lib.mbd_scs
+        L.check(fn(self.handle, sys, C.byref(prm), C.c_void_p(out[0].data_ptr()),
+                   C.c_void_p(out[1].data_ptr()), C.c_void_p(out[2].data_ptr()),
+                   C.c_void_p(af.data_ptr()) if with_freq else None, C.byref(inf)))
         info = {"iterations": inf.iterations, "max_rel_residual": inf.max_rel_residual}
         res = (out[0], out[1], out[2])
         return res + ((af,) if with_freq else ()) + (info,)

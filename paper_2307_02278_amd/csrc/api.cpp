@@ -191,7 +191,7 @@ void allocate_system(Plan& plan, System& S, int R_probes, int m) {
     b.abar = dalloc<double>(plan, (size_t)B * m, by);
     b.bbar = dalloc<double>(plan, (size_t)B * m, by);
     b.adj = dalloc<double>(plan, (size_t)B * 16, by);
-    b.fsum = dalloc<double>(plan, 3 * (size_t)n, by);
+    b.fsum = dalloc<double>(plan, 6 * (size_t)n, by);
   }
   if (plan.prm.krylov_block > 1) {
     BlockWork& bw = b.blk;
@@ -220,18 +220,40 @@ void allocate_system(Plan& plan, System& S, int R_probes, int m) {
   check(hipMemcpy(b.tw, tw.data(), tw.size() * sizeof(R), hipMemcpyHostToDevice), "copy tw");
 }
 
-// Bracket the launches made by f with events when stage timing is on.
+// Bracket the launches that f makes on stream st with events when stage timing is on.
 template <typename F>
-void staged(Plan& plan, int stage, F&& f) {
+void staged_on(Plan& plan, int stage, hipStream_t st, F&& f) {
   if (!plan.timer.on) {
     f();
     return;
   }
   hipEvent_t a = plan.timer.next(), b = plan.timer.next();
-  check(hipEventRecord(a, plan.stream), "event record");
+  check(hipEventRecord(a, st), "event record");
   f();
-  check(hipEventRecord(b, plan.stream), "event record");
+  check(hipEventRecord(b, st), "event record");
   plan.timer.recs.push_back({stage, a, b});
+}
+
+template <typename F>
+void staged(Plan& plan, int stage, F&& f) {
+  staged_on(plan, stage, plan.stream, std::forward<F>(f));
+}
+
+// Start work on the side stream of st, if st has one: it waits for everything enqueued
+// on st so far. Returns nullptr (run on st itself) for streams without a side stream:
+// the internal per-system streams of a batch plan, which overlap whole systems instead.
+SideStream* fork_side(Plan& plan, hipStream_t st) {
+  SideStream* sd = plan.side_of(st);
+  if (!sd) return nullptr;
+  check(hipEventRecord(sd->fork, st), "side fork");
+  check(hipStreamWaitEvent(sd->side, sd->fork, 0), "side fork");
+  return sd;
+}
+
+// Make st wait for the side-stream work enqueued before `done` was recorded.
+void join_side(hipStream_t st, hipStream_t side, hipEvent_t done) {
+  check(hipEventRecord(done, side), "side join");
+  check(hipStreamWaitEvent(st, done, 0), "side join");
 }
 
 template <typename R>
@@ -266,35 +288,49 @@ void create_pair_list(Plan& plan, System& S) {
 // The adjoint matvec C lbar_k (into Lt) together with the bilinear force terms
 // lbar_k^T dC/dR y_k of one reverse step: the pair part, then per grid chunk the
 // reciprocal part with phi of p = g lbar_k (left by the matvec) and with phi of
-// q = g y_k (one more spread and transform of q).
+// q = g y_k (one more spread and transform of q). The pair kernel and the pair force
+// (into the direct half of fsum) run on the side stream beside the grid stages, forked
+// as in matvec_block.
 template <typename R>
 void adjoint_matvec_forces(Plan& plan, System& S) {
   const hipStream_t st = plan.stream;
-  const int nch = plan.B / plan.BG;
+  const int BG = S.BG;
+  const int nch = plan.B / BG;
   SysBuffers& b = S.buf;
   SysBuffers bq = b;
   bq.dv = b.dq;
-  staged(plan, MBD_STAGE_PAIR, [&] { launch_pair<R>(S.geo, b, plan.B, st); });
-  staged(plan, MBD_STAGE_FORCE, [&] { launch_pair_force<R>(S.geo, b, plan.B, st); });
-  for (int c = 0; c < nch; ++c) {
-    staged(plan, MBD_STAGE_SPREAD,
-           [&] { launch_spread<R>(S.geo, b, plan.B, plan.BG, c, 1, st); });
+  SideStream* sd = nullptr;
+  auto pair_work = [&] {
+    sd = S.overlap ? fork_side(plan, st) : nullptr;
+    const hipStream_t ss = sd ? sd->side : st;
+    staged_on(plan, MBD_STAGE_PAIR, ss, [&] { launch_pair<R>(S.geo, b, plan.B, ss); });
+    if (sd) check(hipEventRecord(sd->pair_done, ss), "side join");
+    staged_on(plan, MBD_STAGE_FORCE, ss, [&] { launch_pair_force<R>(S.geo, b, plan.B, ss); });
+  };
+  if (S.overlap != 2) pair_work();
+  for (int c = 0; c < nch; ++c)
+    staged(plan, MBD_STAGE_SPREAD, [&] { launch_spread<R>(S.geo, b, plan.B, BG, c, 1, st); });
+  if (S.overlap == 2) pair_work();
+  for (int c = 0; c < nch; ++c)
     for (int pass = 0; pass < 5; ++pass)
       staged(plan, MBD_STAGE_FFT_X + pass,
-             [&] { launch_fft_pass<R>(S.geo, b, plan.B, plan.BG, c, 1, pass, st); });
+             [&] { launch_fft_pass<R>(S.geo, b, plan.B, BG, c, 1, pass, st); });
+  if (sd) check(hipStreamWaitEvent(st, sd->pair_done, 0), "side join");
+  for (int c = 0; c < nch; ++c) {
     staged(plan, MBD_STAGE_GATHER, [&] {
-      launch_epilogue<R>(S.geo, b, b.lbar, plan.B, plan.BG, c, 1, MBD_C_ALL, st);
+      launch_epilogue<R>(S.geo, b, b.lbar, plan.B, BG, c, 1, MBD_C_ALL, st);
     });
     staged(plan, MBD_STAGE_FORCE,
-           [&] { launch_spme_force<R>(S.geo, b, b.dq, plan.B, plan.BG, c, st); });
+           [&] { launch_spme_force<R>(S.geo, b, b.dq, plan.B, BG, c, st); });
     staged(plan, MBD_STAGE_SPREAD,
-           [&] { launch_spread<R>(S.geo, bq, plan.B, plan.BG, c, 1, st); });
+           [&] { launch_spread<R>(S.geo, bq, plan.B, BG, c, 1, st); });
     for (int pass = 0; pass < 5; ++pass)
       staged(plan, MBD_STAGE_FFT_X + pass,
-             [&] { launch_fft_pass<R>(S.geo, bq, plan.B, plan.BG, c, 1, pass, st); });
+             [&] { launch_fft_pass<R>(S.geo, bq, plan.B, BG, c, 1, pass, st); });
     staged(plan, MBD_STAGE_FORCE,
-           [&] { launch_spme_force<R>(S.geo, b, b.dv, plan.B, plan.BG, c, st); });
+           [&] { launch_spme_force<R>(S.geo, b, b.dv, plan.B, BG, c, st); });
   }
+  if (sd) join_side(st, sd->side, sd->force_done);
 }
 
 // Reverse sweep for one block of probes (their Krylov vectors are still in W).
@@ -317,31 +353,44 @@ void run_backward(Plan& plan, System& S, int l0, int nb) {
 }
 
 // One application of C to the block stored at w (internal layout), into Lt.
-// The grid stages run chunk by chunk (BG right-hand sides at a time) so that one
-// chunk's grid stays resident in the last-level cache between the passes.
+// The grid stages run on st, stage by stage over the grid chunks (BG right-hand sides
+// each): the spreads, then the five transform passes of each chunk, then the gathers,
+// which are the first readers of the direct-space field. With a side stream
+// (S.overlap 1 or 2) the ALU-bound pair kernel runs there concurrently with the
+// HBM-bound grid stages, forked before the spreads (1) or after them, beside the
+// transforms only (2), and joined before the gathers.
 template <typename R>
 void matvec_block(Plan& plan, System& S, const double* w, uint32_t comps) {
   const hipStream_t st = plan.stream;
-  const int nch = plan.B / plan.BG;
-  if (S.geo.replica_cut > 0.0) {
-    // replica method: Omega w + g (sum over images of f T) g w; no Ewald split
-    comps &= (MBD_C_DIAG | MBD_C_DIR);
-    if (comps & MBD_C_DIR)
-      staged(plan, MBD_STAGE_PAIR, [&] { launch_replica(S.geo, S.buf, plan.B, st); });
-  } else if (comps & MBD_C_DIR) {
-    staged(plan, MBD_STAGE_PAIR, [&] { launch_pair<R>(S.geo, S.buf, plan.B, st); });
-  }
-  for (int c = 0; c < nch; ++c) {
-    if (comps & MBD_C_REC) {
+  const int BG = S.BG;
+  const int nch = plan.B / BG;
+  // replica method: Omega w + g (sum over images of f T) g w; no Ewald split
+  if (S.geo.replica_cut > 0.0) comps &= (MBD_C_DIAG | MBD_C_DIR);
+  SideStream* sd = nullptr;
+  auto pair_work = [&] {
+    sd = S.overlap ? fork_side(plan, st) : nullptr;
+    const hipStream_t ss = sd ? sd->side : st;
+    staged_on(plan, MBD_STAGE_PAIR, ss, [&] {
+      if (S.geo.replica_cut > 0.0) launch_replica(S.geo, S.buf, plan.B, ss);
+      else launch_pair<R>(S.geo, S.buf, plan.B, ss);
+    });
+  };
+  const bool rec = (comps & MBD_C_REC) != 0;
+  if ((comps & MBD_C_DIR) && (S.overlap != 2 || !rec)) pair_work();
+  if (rec)
+    for (int c = 0; c < nch; ++c)
       staged(plan, MBD_STAGE_SPREAD,
-             [&] { launch_spread<R>(S.geo, S.buf, plan.B, plan.BG, c, 1, st); });
+             [&] { launch_spread<R>(S.geo, S.buf, plan.B, BG, c, 1, st); });
+  if ((comps & MBD_C_DIR) && S.overlap == 2 && rec) pair_work();
+  if (rec)
+    for (int c = 0; c < nch; ++c)
       for (int pass = 0; pass < 5; ++pass)
         staged(plan, MBD_STAGE_FFT_X + pass,
-               [&] { launch_fft_pass<R>(S.geo, S.buf, plan.B, plan.BG, c, 1, pass, st); });
-    }
+               [&] { launch_fft_pass<R>(S.geo, S.buf, plan.B, BG, c, 1, pass, st); });
+  if (sd) join_side(st, sd->side, sd->pair_done);
+  for (int c = 0; c < nch; ++c)
     staged(plan, MBD_STAGE_GATHER,
-           [&] { launch_epilogue<R>(S.geo, S.buf, w, plan.B, plan.BG, c, 1, comps, st); });
-  }
+           [&] { launch_epilogue<R>(S.geo, S.buf, w, plan.B, BG, c, 1, comps, st); });
 }
 
 template <typename R>
@@ -350,7 +399,7 @@ void run_backward(Plan& plan, System& S, int l0, int nb);
 // Block Lanczos (krylov_block > 1): per batch of B probes, B / kb Krylov blocks run
 // side by side through the same matvecs; each block step replaces the scalar update.
 template <typename R>
-void run_energy_block(Plan& plan, System& S, int sys_index, double* energy) {
+void run_energy_block(Plan& plan, System& S, int sys_index, double* energy, double* sd) {
   const hipStream_t st = plan.stream;
   const int B = plan.B, m = plan.prm.n_steps, R_probes = plan.prm.n_probes;
   const bool fl = sizeof(R) == 4;
@@ -373,13 +422,13 @@ void run_energy_block(Plan& plan, System& S, int sys_index, double* energy) {
     });
   }
   staged(plan, MBD_STAGE_LANCZOS,
-         [&] { launch_energy(S.geo, S.buf, R_probes, energy, plan.status, st); });
+         [&] { launch_energy(S.geo, S.buf, R_probes, energy, sd, plan.status, st); });
 }
 
 template <typename R>
-void run_energy(Plan& plan, System& S, int sys_index, double* energy, bool forces) {
+void run_energy(Plan& plan, System& S, int sys_index, double* energy, double* sd, bool forces) {
   if (plan.prm.krylov_block > 1) {
-    run_energy_block<R>(plan, S, sys_index, energy);
+    run_energy_block<R>(plan, S, sys_index, energy, sd);
     return;
   }
   const hipStream_t st = plan.stream;
@@ -414,7 +463,7 @@ void run_energy(Plan& plan, System& S, int sys_index, double* energy, bool force
     if (forces) run_backward<R>(plan, S, l0, nb);
   }
   staged(plan, MBD_STAGE_LANCZOS,
-         [&] { launch_energy(S.geo, S.buf, R_probes, energy, plan.status, st); });
+         [&] { launch_energy(S.geo, S.buf, R_probes, energy, sd, plan.status, st); });
 }
 
 mbd_status fail(mbd_status code, const std::string& msg) {
@@ -422,9 +471,198 @@ mbd_status fail(mbd_status code, const std::string& msg) {
   return code;
 }
 
+
+// ---- launch shapes and their tuner ---------------------------------------------------
+// A shape only changes how a system's matvec is laid out on the GPU: work-groups of the
+// list kernel, lanes per target and a side stream for the pair kernel leave every result
+// bit unchanged; the grid chunk width changes the summation order of the spread and the
+// gather (sub-lanes share a stencil below 64 right-hand sides per chunk).
+
+constexpr mbd_shape kBuiltinShape = {0, 0, 0, 1};
+
+bool valid_shape(const mbd_shape& sh, int B) {
+  const bool pow2chunk = sh.grid_chunk == 0 || (sh.grid_chunk > 0 && sh.grid_chunk <= 64 &&
+                                                is_pow2(sh.grid_chunk) && B % sh.grid_chunk == 0);
+  return sh.pair_wg_per_cu >= 0 && sh.pair_wg_per_cu <= 64 &&
+         (sh.pair_subsets == 0 || sh.pair_subsets == 1 || sh.pair_subsets == 2 ||
+          sh.pair_subsets == 4) &&
+         pow2chunk && sh.overlap >= 0 && sh.overlap <= 2;
+}
+
+void apply_shape(const Plan& plan, System& S, const mbd_shape& sh) {
+  S.shape = sh;
+  S.geo.pair_blocks = sh.pair_wg_per_cu * plan.cus;
+  S.geo.pair_ns = sh.pair_subsets;
+  S.BG = sh.grid_chunk > 0 ? sh.grid_chunk : plan.BG;
+  // the per-system streams of a batch plan have no side stream
+  S.overlap = plan.batch ? 0 : sh.overlap;
+  S.shape.overlap = S.overlap;
+}
+
+std::string shape_key(const Plan& plan, const System& S) {
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s|N=%d|K=%dx%dx%d|p=%d|B=%d|prec=%d|forces=%d|batch=%d",
+                plan.arch.c_str(), S.geo.n, S.geo.K[0], S.geo.K[1], S.geo.K[2], S.geo.p, plan.B,
+                plan.prec, plan.forces ? 1 : 0, plan.batch ? 1 : 0);
+  return buf;
+}
+
+// Value of an integer or real field `"name": v` in one JSON line (false if absent).
+bool json_number(const std::string& line, const char* name, double& v) {
+  const std::string tag = std::string("\"") + name + "\":";
+  const size_t at = line.find(tag);
+  if (at == std::string::npos) return false;
+  const char* p = line.c_str() + at + tag.size();
+  char* end = nullptr;
+  v = std::strtod(p, &end);
+  return end != p;
+}
+
+// The last cached shape for key in a JSON-lines file, if any.
+bool cache_lookup(const char* path, const std::string& key, mbd_shape& sh, double& ms) {
+  if (!path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  bool found = false;
+  char line[1024];
+  const std::string tag = "\"key\": \"" + key + "\"";
+  while (std::fgets(line, sizeof line, f)) {
+    const std::string l(line);
+    if (l.find(tag) == std::string::npos) continue;
+    double a, b, c, d, t = 0.0;
+    if (json_number(l, "pair_wg_per_cu", a) && json_number(l, "pair_subsets", b) &&
+        json_number(l, "grid_chunk", c) && json_number(l, "overlap", d)) {
+      json_number(l, "matvec_ms", t);
+      sh = mbd_shape{(int32_t)a, (int32_t)b, (int32_t)c, (int32_t)d};
+      ms = t;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void cache_store(const char* path, const std::string& key, const mbd_shape& sh, double ms) {
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f,
+               "{\"key\": \"%s\", \"pair_wg_per_cu\": %d, \"pair_subsets\": %d, "
+               "\"grid_chunk\": %d, \"overlap\": %d, \"matvec_ms\": %.5f}\n",
+               key.c_str(), sh.pair_wg_per_cu, sh.pair_subsets, sh.grid_chunk, sh.overlap, ms);
+  std::fclose(f);
+}
+
+// Fastest of `reps` timed applications of C to the probe block in W[0] (after one
+// untimed application), in milliseconds, with the system's current shape.
+template <typename R>
+double time_matvec(Plan& plan, System& S, int reps) {
+  hipEvent_t a = nullptr, b = nullptr;
+  check(hipEventCreate(&a), "event create");
+  check(hipEventCreate(&b), "event create");
+  float best = 1e30f;
+  try {
+    matvec_block<R>(plan, S, S.buf.W, MBD_C_ALL);
+    for (int r = 0; r < reps; ++r) {
+      check(hipEventRecord(a, plan.stream), "event record");
+      matvec_block<R>(plan, S, S.buf.W, MBD_C_ALL);
+      check(hipEventRecord(b, plan.stream), "event record");
+      check(hipEventSynchronize(b), "event sync");
+      float t = 0.f;
+      check(hipEventElapsedTime(&t, a, b), "event time");
+      best = std::min(best, t);
+    }
+  } catch (...) {
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    throw;
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return best;
+}
+
+// Coordinate search over the shape knobs on the system's real data: the pair kernel's
+// residency together with the side stream, then its lanes per target, then the grid
+// chunk width, then the residency once more under the chosen chunk.
+template <typename R>
+void tune_system(Plan& plan, System& S, int sys_index) {
+  const int B = plan.B;
+  launch_probes(S.geo, S.buf, B, B, 0, plan.prm.seed, sys_index, sizeof(R) == 4, plan.stream);
+  const bool list = S.buf.pg_T != nullptr && S.geo.replica_cut <= 0.0;
+  mbd_shape best = kBuiltinShape;
+  apply_shape(plan, S, best);
+  double tbest = time_matvec<R>(plan, S, 3);
+  auto trial = [&](const mbd_shape& sh) {
+    apply_shape(plan, S, sh);
+    const double t = time_matvec<R>(plan, S, 3);
+    if (t < tbest) {
+      tbest = t;
+      best = S.shape;
+    }
+  };
+  auto residency = [&] {
+    const mbd_shape base = best;
+    for (int ov = plan.batch ? 0 : 2; ov >= 0; --ov)
+      for (int wg : {0, 1, 2, 3, 4}) {
+        if (!list && wg > 0) continue;
+        mbd_shape sh = base;
+        sh.overlap = ov;
+        sh.pair_wg_per_cu = wg;
+        if (sh.overlap != base.overlap || sh.pair_wg_per_cu != base.pair_wg_per_cu) trial(sh);
+      }
+  };
+  residency();
+  if (list) {
+    const mbd_shape base = best;
+    for (int ns : {1, 2, 4}) {
+      if (ns * B < 64) continue;
+      mbd_shape sh = base;
+      sh.pair_subsets = ns;
+      trial(sh);
+    }
+  }
+  {
+    const mbd_shape base = best;
+    const int dflt = plan.BG;
+    for (int bg : {8, 16, 32, 64}) {
+      if (bg > B || B % bg != 0 || bg == (base.grid_chunk ? base.grid_chunk : dflt)) continue;
+      if (bg < dflt / 4) continue;
+      mbd_shape sh = base;
+      sh.grid_chunk = bg;
+      trial(sh);
+    }
+  }
+  residency();
+  apply_shape(plan, S, best);
+  S.shape_source = MBD_SHAPE_MEASURED;
+  S.tune_ms = tbest;
+}
+
 }  // namespace
 
 void set_error(const std::string& msg) { g_last_error = msg; }
+
+SideStream* Plan::side_of(hipStream_t origin) {
+  for (SideStream& s : sides)
+    if (s.origin == origin) return &s;
+  return nullptr;
+}
+
+// Side stream and events for one origin stream (created right after the origin so that
+// the two map to different hardware queues).
+void add_side(Plan& plan, hipStream_t origin) {
+  for (const SideStream& s : plan.sides)
+    if (s.origin == origin) return;
+  SideStream s;
+  s.origin = origin;
+  check(hipStreamCreateWithFlags(&s.side, hipStreamNonBlocking), "stream create");
+  plan.sides.push_back(s);
+  SideStream& t = plan.sides.back();
+  check(hipEventCreateWithFlags(&t.fork, hipEventDisableTiming), "event create");
+  check(hipEventCreateWithFlags(&t.pair_done, hipEventDisableTiming), "event create");
+  check(hipEventCreateWithFlags(&t.force_done, hipEventDisableTiming), "event create");
+}
 
 hipEvent_t StageTimer::next() {
   if (used == pool.size()) {
@@ -530,6 +768,11 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
   }
   for (int a = 0; a < 3; ++a)
     if (prm.grid[a] < 0) return fail(MBD_E_ARG, "grid sizes must be >= 0");
+  if (prm.tune != MBD_TUNE_OFF && prm.tune != MBD_TUNE_MEASURE && prm.tune != MBD_TUNE_GIVEN)
+    return fail(MBD_E_ARG, "tune must be MBD_TUNE_OFF, MBD_TUNE_MEASURE or MBD_TUNE_GIVEN");
+  if (prm.tune == MBD_TUNE_GIVEN && !valid_shape(prm.shape, prm.block))
+    return fail(MBD_E_ARG, "shape: pair_wg_per_cu in [0, 64], pair_subsets 0/1/2/4, grid_chunk "
+                           "0 or a power of two <= 64 dividing block, overlap 0/1/2");
 
   const int BG_plan = std::min(prm.block, prm.precision == MBD_PREC_FP64 ? 16 : 64);
   std::vector<Geometry> geos(n_sys);
@@ -589,9 +832,20 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
   plan.forces = prm.want_forces != 0;
   plan.use_graph = prm.graph != 0;
   plan.stream = static_cast<hipStream_t>(stream);
+  plan.batch = n_sys > 1;
   hipGetDevice(&plan.device);
+  {
+    hipDeviceProp_t dp;
+    if (hipGetDeviceProperties(&dp, plan.device) == hipSuccess) {
+      plan.cus = std::max(1, dp.multiProcessorCount);
+      plan.arch = dp.gcnArchName;
+      const size_t colon = plan.arch.find(':');
+      if (colon != std::string::npos) plan.arch.resize(colon);
+    }
+  }
   try {
     size_t sb = 0;
+    add_side(plan, plan.stream);
     plan.status = dalloc<uint32_t>(plan, 1, sb);
     check(hipMemset(plan.status, 0, sizeof(uint32_t)), "clear status");
     plan.sys.resize(n_sys);
@@ -679,14 +933,37 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
         if (plan.B >= 16 || plan.forces) create_pair_list<float>(plan, S);
       }
       check(hipGetLastError(), "setup launch");
+      // launch shape: built in, given, cached or measured on this system
+      if (prm.tune == MBD_TUNE_GIVEN) {
+        apply_shape(plan, S, prm.shape);
+        S.shape_source = MBD_SHAPE_GIVEN;
+      } else if (prm.tune == MBD_TUNE_MEASURE && g.replica_cut <= 0.0) {
+        const std::string key = shape_key(plan, S);
+        mbd_shape sh;
+        double ms = 0.0;
+        if (cache_lookup(prm.tune_cache, key, sh, ms) && valid_shape(sh, plan.B)) {
+          apply_shape(plan, S, sh);
+          S.shape_source = MBD_SHAPE_CACHED;
+          S.tune_ms = ms;
+        } else {
+          if (plan.prec == MBD_PREC_FP64) tune_system<double>(plan, S, s);
+          else tune_system<float>(plan, S, s);
+          cache_store(prm.tune_cache, key, S.shape, S.tune_ms);
+        }
+      } else {
+        apply_shape(plan, S, kBuiltinShape);
+        S.shape_source = MBD_SHAPE_BUILTIN;
+      }
     }
     if (plan.use_graph) {
       check(hipStreamCreateWithFlags(&plan.gstream, hipStreamNonBlocking), "stream create");
+      add_side(plan, plan.gstream);
       check(hipEventCreateWithFlags(&plan.g_in, hipEventDisableTiming), "event create");
       check(hipEventCreateWithFlags(&plan.g_out, hipEventDisableTiming), "event create");
       size_t nat = 0, gb = 0;
       for (const auto& S : plan.sys) nat += (size_t)S.geo.n;
       plan.e_out = dalloc<double>(plan, n_sys, gb);
+      plan.sd_out = dalloc<double>(plan, n_sys, gb);
       if (plan.forces) plan.f_out = dalloc<double>(plan, 3 * nat, gb);
     }
     if (n_sys > 1) {
@@ -745,6 +1022,9 @@ mbd_status mbd_plan_info(mbd_plan plan, int32_t sys, mbd_info* info) {
   info->n_pairs = P.prec == MBD_PREC_FP64
                       ? mbd::count_pairs<double>(g, P.sys[sys].buf, P.stream)
                       : mbd::count_pairs<float>(g, P.sys[sys].buf, P.stream);
+  info->shape = P.sys[sys].shape;
+  info->shape_source = P.sys[sys].shape_source;
+  info->tune_ms = P.sys[sys].tune_ms;
   if (info->n_pairs < 0) return fail(MBD_E_HIP, "pair count failed");
   return MBD_OK;
 }
@@ -794,7 +1074,7 @@ namespace {
 
 // Enqueue one full evaluation (all systems) on plan.stream: clear the status word,
 // fork to the internal streams, run every system, join back.
-void enqueue_execute(Plan& P, double* energy, double* forces) {
+void enqueue_execute(Plan& P, double* energy, double* sd, double* forces) {
   const hipStream_t caller = P.stream;
   fill_int(reinterpret_cast<int*>(P.status), 0, 1, caller);
   const bool fork = !P.pool.empty();
@@ -807,9 +1087,11 @@ void enqueue_execute(Plan& P, double* energy, double* forces) {
     for (int s = 0; s < (int)P.sys.size(); ++s) {
       System& S = P.sys[s];
       if (fork) P.stream = P.pool[P.sys_stream[s]];  // this system's work goes to its stream
-      if (forces) fill_double(S.buf.fsum, 0.0, 3 * (size_t)S.geo.n, P.stream);
-      if (P.prec == MBD_PREC_FP64) run_energy<double>(P, S, s, energy + s, forces != nullptr);
-      else run_energy<float>(P, S, s, energy + s, forces != nullptr);
+      if (forces) fill_double(S.buf.fsum, 0.0, 6 * (size_t)S.geo.n, P.stream);
+      double* sds = sd ? sd + s : nullptr;
+      if (P.prec == MBD_PREC_FP64)
+        run_energy<double>(P, S, s, energy + s, sds, forces != nullptr);
+      else run_energy<float>(P, S, s, energy + s, sds, forces != nullptr);
       if (forces)
         staged(P, MBD_STAGE_ADJOINT, [&] {
           launch_forces_finish(S.geo, S.buf, P.prm.n_probes, forces + 3 * off, P.stream);
@@ -831,7 +1113,7 @@ void enqueue_execute(Plan& P, double* energy, double* forces) {
 }  // namespace
 }  // namespace mbd
 
-mbd_status mbd_execute(mbd_plan plan, double* energy, double* forces) {
+mbd_status mbd_execute(mbd_plan plan, double* energy, double* forces, double* energy_sd) {
   using namespace mbd;
   if (!plan || !energy) return fail(MBD_E_ARG, "NULL argument");
   Plan& P = plan->plan;
@@ -839,7 +1121,7 @@ mbd_status mbd_execute(mbd_plan plan, double* energy, double* forces) {
     return fail(MBD_E_STATE, "forces requested from a plan created with want_forces = 0");
   try {
     if (!P.use_graph || P.timer.on) {
-      enqueue_execute(P, energy, forces);
+      enqueue_execute(P, energy, energy_sd, forces);
     } else {
       const int gi = forces ? 1 : 0;
       const hipStream_t caller = P.stream;
@@ -848,7 +1130,7 @@ mbd_status mbd_execute(mbd_plan plan, double* energy, double* forces) {
         P.stream = P.gstream;  // the sequence is recorded from the plan's own stream
         check(hipStreamBeginCapture(P.gstream, hipStreamCaptureModeRelaxed), "begin capture");
         try {
-          enqueue_execute(P, P.e_out, forces ? P.f_out : nullptr);
+          enqueue_execute(P, P.e_out, P.sd_out, forces ? P.f_out : nullptr);
         } catch (...) {
           P.stream = caller;
           hipStreamEndCapture(P.gstream, &g);
@@ -871,6 +1153,9 @@ mbd_status mbd_execute(mbd_plan plan, double* energy, double* forces) {
       for (const auto& S : P.sys) nat += (size_t)S.geo.n;
       check(hipMemcpyAsync(energy, P.e_out, sizeof(double) * P.sys.size(),
                            hipMemcpyDeviceToDevice, P.stream), "copy energy");
+      if (energy_sd)
+        check(hipMemcpyAsync(energy_sd, P.sd_out, sizeof(double) * P.sys.size(),
+                             hipMemcpyDeviceToDevice, P.stream), "copy energy s.d.");
       if (forces)
         check(hipMemcpyAsync(forces, P.f_out, sizeof(double) * 3 * nat, hipMemcpyDeviceToDevice,
                              P.stream), "copy forces");
@@ -957,14 +1242,52 @@ mbd_status mbd_get_quadrature(mbd_plan plan, int32_t sys, double* q) {
   return MBD_OK;
 }
 
-mbd_status mbd_scs(mbd_plan plan, int32_t sys, const mbd_scs_params* prm_in, double* alpha_scs,
-                   double* omega_scs, double* rvdw_scs, double* alpha_freq, mbd_scs_info* info) {
-  using namespace mbd;
-  if (!plan || !prm_in || !alpha_scs || !omega_scs || !rvdw_scs)
-    return fail(MBD_E_ARG, "NULL argument");
-  Plan& P = plan->plan;
+}  // extern "C"
+
+namespace mbd {
+namespace {
+
+// Doubles of one screening workspace (n atoms, nq frequencies, nblk row blocks), every
+// piece starting on a 256-byte boundary; carve_scs lays it out in this order.
+constexpr size_t kScsAlign = 32;
+size_t scs_piece(size_t count) { return (count + kScsAlign - 1) / kScsAlign * kScsAlign; }
+
+size_t scs_doubles(int n, int nq, int nblk) {
+  const size_t ncol = 3 * (size_t)nq, vec = (size_t)n * 3 * ncol;
+  return scs_piece(4 * (size_t)n) + 2 * scs_piece((size_t)n * nq) + 5 * scs_piece(vec) +
+         scs_piece((size_t)nblk * 2 * ncol) + scs_piece(2 * ncol) + scs_piece(8 * ncol) +
+         scs_piece(1) + 2 * scs_piece((size_t)nq);
+}
+
+void carve_scs(double* base, ScsWork& w, double*& u_d, double*& w_d) {
+  const size_t ncol = (size_t)w.ncol, vec = (size_t)w.n * 3 * ncol;
+  double* p = base;
+  auto take = [&](size_t count) {
+    double* q = p;
+    p += scs_piece(count);
+    return q;
+  };
+  w.locd = take(4 * (size_t)w.n);
+  w.ainv = take((size_t)w.n * w.nq);
+  w.sig2 = take((size_t)w.n * w.nq);
+  w.x = take(vec);
+  w.r = take(vec);
+  w.z = take(vec);
+  w.p = take(vec);
+  w.q = take(vec);
+  w.part = take((size_t)w.nblk * 2 * ncol);
+  w.sums = take(2 * ncol);
+  w.sc = take(8 * ncol);
+  w.nact = reinterpret_cast<int*>(take(1));
+  u_d = take((size_t)w.nq);
+  w_d = take((size_t)w.nq);
+}
+
+// Validated screening parameters and the workspace shape of one system.
+mbd_status scs_prepare(Plan& P, int32_t sys, const mbd_scs_params* prm_in, mbd_scs_params& prm,
+                       ScsWork& w) {
   if (sys < 0 || sys >= (int)P.sys.size()) return fail(MBD_E_ARG, "system index out of range");
-  mbd_scs_params prm = *prm_in;
+  prm = *prm_in;
   if (prm.n_freq == 0) prm.n_freq = 15;
   if (prm.n_freq < 1 || prm.n_freq > 31) return fail(MBD_E_ARG, "n_freq must be in [1, 31]");
   if (!std::isfinite(prm.freq_scale) || !std::isfinite(prm.tol))
@@ -972,54 +1295,35 @@ mbd_status mbd_scs(mbd_plan plan, int32_t sys, const mbd_scs_params* prm_in, dou
   if (prm.freq_scale <= 0.0) prm.freq_scale = 0.6;
   if (prm.tol <= 0.0) prm.tol = 1e-10;
   if (prm.max_iter <= 0) prm.max_iter = 1000;
-  System& S = P.sys[sys];
-  const hipStream_t st = P.stream;
-  ScsWork w;
-  w.n = S.geo.n;
+  w.n = P.sys[sys].geo.n;
   w.nq = prm.n_freq + 1;  // the static point u = 0, then the quadrature nodes
   w.ncol = 3 * w.nq;
   w.nblk = std::max(1, std::min(512, (3 * w.n + 127) / 128));
+  return MBD_OK;
+}
+
+// The screening solve of one system with its workspace at `ws` (device, scs_doubles
+// long). Host arrays are fixed-size (n_freq <= 31): nothing is allocated here.
+mbd_status scs_run(Plan& P, int32_t sys, const mbd_scs_params& prm, ScsWork& w, double* ws,
+                   double* alpha_scs, double* omega_scs, double* rvdw_scs, double* alpha_freq,
+                   mbd_scs_info* info) {
+  System& S = P.sys[sys];
+  const hipStream_t st = P.stream;
   // node 0: u = 0 (no weight); nodes 1..n: u = L (1 + x) / (1 - x), w = 2 L w_x / (1 - x)^2
-  std::vector<double> x(prm.n_freq), wx(prm.n_freq), u(w.nq, 0.0), wq(w.nq, 0.0);
-  gauss_legendre(prm.n_freq, x.data(), wx.data());
+  double x[32], wx[32], u[32] = {0.0}, wq[32] = {0.0}, sc[8 * 96];
+  gauss_legendre(prm.n_freq, x, wx);
   for (int q = 0; q < prm.n_freq; ++q) {
     u[q + 1] = prm.freq_scale * (1.0 + x[q]) / (1.0 - x[q]);
     wq[q + 1] = wx[q] * 2.0 * prm.freq_scale / ((1.0 - x[q]) * (1.0 - x[q]));
   }
-  std::vector<void*> mem;
-  auto alloc = [&](size_t count) {
-    void* p = nullptr;
-    if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(double)) != hipSuccess)
-      throw std::bad_alloc();
-    mem.push_back(p);
-    return static_cast<double*>(p);
-  };
-  auto release = [&] {
-    for (void* p : mem) hipFree(p);
-    mem.clear();
-  };
+  double *u_d = nullptr, *w_d = nullptr;
+  carve_scs(ws, w, u_d, w_d);
   int iters = 0, nact = 0;
   uint32_t stat = 0;
-  std::vector<double> sc;
   try {
-    const size_t vec = (size_t)w.n * 3 * w.ncol;
-    w.locd = alloc(4 * (size_t)w.n);
-    w.ainv = alloc((size_t)w.n * w.nq);
-    w.sig2 = alloc((size_t)w.n * w.nq);
-    w.x = alloc(vec);
-    w.r = alloc(vec);
-    w.z = alloc(vec);
-    w.p = alloc(vec);
-    w.q = alloc(vec);
-    w.part = alloc((size_t)w.nblk * 2 * w.ncol);
-    w.sums = alloc(2 * (size_t)w.ncol);
-    w.sc = alloc(8 * (size_t)w.ncol);
-    w.nact = reinterpret_cast<int*>(alloc(1));
-    double* u_d = alloc(w.nq);
-    double* w_d = alloc(w.nq);
     check(hipStreamSynchronize(st), "scs");
-    check(hipMemcpy(u_d, u.data(), sizeof(double) * w.nq, hipMemcpyHostToDevice), "scs nodes");
-    check(hipMemcpy(w_d, wq.data(), sizeof(double) * w.nq, hipMemcpyHostToDevice), "scs nodes");
+    check(hipMemcpy(u_d, u, sizeof(double) * w.nq, hipMemcpyHostToDevice), "scs nodes");
+    check(hipMemcpy(w_d, wq, sizeof(double) * w.nq, hipMemcpyHostToDevice), "scs nodes");
     fill_int(reinterpret_cast<int*>(P.status), 0, 1, st);
     launch_scs_prepare(S.geo, S.buf, S.src.alpha, S.src.omega, S.src.r_vdw, u_d, w, st);
     launch_scs_init(w, st);
@@ -1034,21 +1338,14 @@ mbd_status mbd_scs(mbd_plan plan, int32_t sys, const mbd_scs_params* prm_in, dou
     launch_scs_output(S.buf, w, w_d, S.src.alpha, S.src.r_vdw, alpha_scs, omega_scs, rvdw_scs,
                       alpha_freq, st);
     check(hipGetLastError(), "scs output");
-    sc.resize(8 * (size_t)w.ncol);
-    check(hipMemcpyAsync(sc.data(), w.sc, sizeof(double) * sc.size(), hipMemcpyDeviceToHost, st),
+    check(hipMemcpyAsync(sc, w.sc, sizeof(double) * 8 * w.ncol, hipMemcpyDeviceToHost, st),
           "scs");
     check(hipMemcpyAsync(&stat, P.status, sizeof(stat), hipMemcpyDeviceToHost, st), "scs");
     check(hipStreamSynchronize(st), "scs");
-  } catch (const std::bad_alloc&) {
-    hipStreamSynchronize(st);
-    release();
-    return fail(MBD_E_OOM, "device allocation failed (scs workspace)");
   } catch (const HipError& e) {
     hipStreamSynchronize(st);
-    release();
     return fail(MBD_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
   }
-  release();
   if (info) {
     // sc rows 4 (||r||^2) and 6 (||E_k||^2)
     double worst = 0.0;
@@ -1065,12 +1362,48 @@ mbd_status mbd_scs(mbd_plan plan, int32_t sys, const mbd_scs_params* prm_in, dou
   return MBD_OK;
 }
 
+
+}  // namespace
+}  // namespace mbd
+
+extern "C" {
+
+mbd_status mbd_scs(mbd_plan plan, int32_t sys, const mbd_scs_params* prm_in, double* alpha_scs,
+                   double* omega_scs, double* rvdw_scs, double* alpha_freq, mbd_scs_info* info) {
+  using namespace mbd;
+  if (!plan || !prm_in || !alpha_scs || !omega_scs || !rvdw_scs)
+    return fail(MBD_E_ARG, "NULL argument");
+  Plan& P = plan->plan;
+  mbd_scs_params prm;
+  ScsWork w;
+  const mbd_status v = scs_prepare(P, sys, prm_in, prm, w);
+  if (v != MBD_OK) return v;
+  void* ws = nullptr;
+  if (hipStreamSynchronize(P.stream) != hipSuccess)
+    return fail(MBD_E_HIP, "stream synchronize failed");
+  if (hipMalloc(&ws, sizeof(double) * scs_doubles(w.n, w.nq, w.nblk)) != hipSuccess)
+    return fail(MBD_E_OOM, "device allocation failed (scs workspace)");
+  const mbd_status r = scs_run(P, sys, prm, w, static_cast<double*>(ws), alpha_scs, omega_scs,
+                               rvdw_scs, alpha_freq, info);
+  hipStreamSynchronize(P.stream);
+  hipFree(ws);
+  return r;
+}
+
 mbd_status mbd_plan_destroy(mbd_plan plan) {
   if (!plan) return MBD_OK;
   hipStreamSynchronize(plan->plan.stream);
   for (hipStream_t q : plan->plan.pool)
     if (q) hipStreamSynchronize(q);
   if (plan->plan.gstream) hipStreamSynchronize(plan->plan.gstream);
+  for (const mbd::SideStream& s : plan->plan.sides) {
+    if (s.side) {
+      hipStreamSynchronize(s.side);
+      hipStreamDestroy(s.side);
+    }
+    for (hipEvent_t e : {s.fork, s.pair_done, s.force_done})
+      if (e) hipEventDestroy(e);
+  }
   for (hipGraphExec_t g : plan->plan.gexec)
     if (g) hipGraphExecDestroy(g);
   if (plan->plan.g_in) hipEventDestroy(plan->plan.g_in);

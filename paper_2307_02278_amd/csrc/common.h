@@ -47,6 +47,9 @@ struct Geometry {
   double beta, damp_d;
   double replica_cut;    // > 0: replica method (damped tensor over images within this cutoff)
   int n_images;          // replica image vectors
+  // launch shape of the direct-space list kernels (set by the plan or its tuner)
+  int pair_blocks;       // work-groups of a launch; 0 => one per 16-atom group
+  int pair_ns;           // target subsets per wavefront (1, 2, 4); 0 => size rule
 };
 
 // Cells are numbered along a Morton (Z-order) curve so that consecutive sorted
@@ -149,13 +152,20 @@ struct SysBuffers {
   double* abar = nullptr;      // [B][m] dQ/da_k, then the full adjoint of a_k
   double* bbar = nullptr;      // [B][m] dQ/d nrm_k (k >= 1)
   double* adj = nullptr;       // [B][8] per-step adjoint scalars
-  double* fsum = nullptr;      // [n][3] sum over probes and steps of l-bar^T dC/dR y (sorted)
+  double* fsum = nullptr;      // [2][n][3] sums over probes and steps of l-bar^T dC/dR y
+                               // (sorted): [0] reciprocal part, [1] direct (pair) part
   BlockWork blk;               // block Lanczos workspace (krylov_block > 1)
 };
 
 struct System {
   Geometry geo;
   SysBuffers buf;
+  int BG = 64;                 // right-hand sides per grid chunk (divides the block)
+  int overlap = 1;             // pair kernel on the side stream: 0 no, 1 forked before the
+                               // spreads, 2 forked after them (beside the transforms)
+  mbd_shape shape{};           // launch shape in use (reported by mbd_plan_info)
+  int shape_source = 0;        // MBD_SHAPE_* : where the shape came from
+  double tune_ms = 0.0;        // measured matvec time of that shape (0 if not measured)
   mbd_system src;              // caller's arrays (alpha, omega, r_vdw stay caller-owned)
   double host_cell[9];
   size_t bytes = 0;
@@ -171,6 +181,15 @@ struct StageTimer {
   hipEvent_t next();
 };
 
+// A side stream forked from one of the plan's streams (the caller's or the capture
+// stream): each matvec runs its direct-space pair kernel there,
+// concurrently with the grid stages on the origin stream, and joins by events.
+struct SideStream {
+  hipStream_t origin = nullptr;
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, pair_done = nullptr, force_done = nullptr;
+};
+
 struct Plan {
   std::vector<System> sys;
   bool forces = false;         // buffers for the reverse sweep exist
@@ -180,6 +199,9 @@ struct Plan {
   int BG;                      // RHS per grid chunk
   hipStream_t stream = nullptr;
   int device = 0;
+  int cus = 256;               // compute units of the device
+  std::string arch;            // device architecture name (tuning cache key)
+  bool batch = false;          // more than one system (per-system streams, no side stream)
   uint32_t* status = nullptr;  // device status word
   bool executed = false;
   std::vector<void*> allocations;
@@ -198,6 +220,11 @@ struct Plan {
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   double* e_out = nullptr;       // [n_sys]
   double* f_out = nullptr;       // [sum n][3] (forces plans)
+  double* sd_out = nullptr;      // [n_sys] standard deviation of the energy estimate
+  // Side streams of the caller's stream and of the capture stream, created with the
+  // plan. The per-system streams of a batch plan have none.
+  std::vector<SideStream> sides;
+  SideStream* side_of(hipStream_t origin);  // nullptr if origin has no side stream
 };
 
 // ---------------------------------------------------------------------------
@@ -246,7 +273,7 @@ void launch_finish_norm(const SysBuffers& b, int B, int nb, int k, int m, int pr
 void launch_tridiag(const SysBuffers& b, int nb, int m, int probe0, uint32_t* status,
                     hipStream_t st);
 void launch_energy(const Geometry& g, const SysBuffers& b, int R, double* energy_out,
-                   uint32_t* status, hipStream_t st);
+                   double* sd_out, uint32_t* status, hipStream_t st);
 void launch_pack(const Geometry& g, const SysBuffers& b, const double* v, int nrhs, int B,
                  bool use_float, hipStream_t st);
 void launch_unpack(const Geometry& g, const SysBuffers& b, double* out, int nrhs, int B,

@@ -262,7 +262,8 @@ k_tridiag(int m, int probe0, const double* __restrict__ a, const double* __restr
 // E = 1/2 (3N / R) sum_l Q_l - 3/2 sum_i omega_i, summed in probe order.
 __global__ void k_energy(int n, int R, const double* __restrict__ q,
                          const double* __restrict__ g, const double* __restrict__ om2,
-                         double* __restrict__ out, uint32_t* __restrict__ status) {
+                         double* __restrict__ out, double* __restrict__ sd_out,
+                         uint32_t* __restrict__ status) {
   __shared__ double red[256];
   double so = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) so += sqrt(om2[i]);
@@ -278,6 +279,14 @@ __global__ void k_energy(int n, int R, const double* __restrict__ q,
     const double E = 0.5 * (3.0 * n / R) * sq - 1.5 * red[0];
     out[0] = E;
     if (!isfinite(E)) atomicOr(status, kErrNonfinite);
+    if (sd_out) {
+      // spread of the R samples of the trace estimator (two passes, fixed order)
+      const double mean = sq / R;
+      double ss = 0.0;
+      for (int l = 0; l < R; ++l) ss += (q[l] - mean) * (q[l] - mean);
+      sd_out[0] = R > 1 ? 0.5 * (3.0 * n) * sqrt(ss / (R - 1)) / sqrt((double)R)
+                        : __builtin_nan("");
+    }
   }
   (void)g;
 }
@@ -584,14 +593,16 @@ __global__ void k_fill_double(double* __restrict__ p, double v, size_t count) {
   if (t < count) p[t] = v;
 }
 
-// F = -dE/dR = -1/2 (3N / R) dsum/dR, back to caller order.
+// F = -dE/dR = -1/2 (3N / R) dsum/dR, back to caller order; dsum/dR is the sum of
+// the reciprocal half and the direct (pair) half of fsum.
 __global__ void k_forces_finish(int n, int R, const int* __restrict__ perm,
                                 const double* __restrict__ fsum, double* __restrict__ out) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const double sc = -0.5 * (3.0 * n / R);
   const int i = perm[s];
-  for (int a = 0; a < 3; ++a) out[3 * i + a] = sc * fsum[3 * s + a];
+  for (int a = 0; a < 3; ++a)
+    out[3 * i + a] = sc * (fsum[3 * s + a] + fsum[3 * ((size_t)n + s) + a]);
 }
 
 inline int rb_for(int B) { return B >= 64 ? 64 : B; }
@@ -681,8 +692,8 @@ void launch_tridiag(const SysBuffers& b, int nb, int m, int probe0, uint32_t* st
 }
 
 void launch_energy(const Geometry& geo, const SysBuffers& b, int R, double* energy_out,
-                   uint32_t* status, hipStream_t st) {
-  k_energy<<<1, 256, 0, st>>>(geo.n, R, b.q, b.g, b.om2, energy_out, status);
+                   double* sd_out, uint32_t* status, hipStream_t st) {
+  k_energy<<<1, 256, 0, st>>>(geo.n, R, b.q, b.g, b.om2, energy_out, sd_out, status);
 }
 
 

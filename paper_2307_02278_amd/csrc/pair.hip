@@ -21,6 +21,8 @@
 //    (k_pair_list) streams a group's tensors through LDS once and applies them to
 //    all right-hand sides, one lane per right-hand side, so every source dipole
 //    load serves all of the group's targets within range.
+#include <algorithm>
+
 #include "common.h"
 #include "mbd_math.h"
 
@@ -311,11 +313,14 @@ k_pair_build(const Geometry geo, const int* __restrict__ cell_start,
   }
 }
 
-// E_dir of one group per work-group: WPB wavefronts, each with 64 / NSUB right-hand
-// sides x NSUB target subsets (lane = rhs + BW * subset), so B = 64 WPB / NSUB. More
-// subsets give more wavefronts per group (small systems) and fewer target slots per
-// lane. Tensors of CH candidates at a time are staged in LDS; the wave-uniform target
-// mask skips out-of-range (target, source) pairs.
+// E_dir of one group at a time per work-group: WPB wavefronts, each with 64 / NSUB
+// right-hand sides x NSUB target subsets (lane = rhs + BW * subset), so
+// B = 64 WPB / NSUB. More subsets give more wavefronts per group (small systems) and
+// fewer target slots per lane. Tensors of CH candidates at a time are staged in LDS;
+// the wave-uniform target mask skips out-of-range (target, source) pairs.
+// The launch may hold fewer work-groups than groups: each then walks its XCD's range
+// of groups with a stride, which leaves compute units and LDS free for the grid
+// stages running beside it on another stream.
 template <typename R, int NSUB, int WPB>
 __global__ void __launch_bounds__(64 * WPB)
 k_pair_list(const Geometry geo, const int2* __restrict__ hdr, const R* __restrict__ Tg,
@@ -333,10 +338,13 @@ k_pair_list(const Geometry geo, const int2* __restrict__ hdr, const R* __restric
   const int lane = tid & 63;
   const int rhs = (tid >> 6) * BW + lane % BW;
   const int sub = lane / BW;
-  // XCD-aware: contiguous ranges of groups per XCD (blocks are dealt round-robin)
-  const int per = (gridDim.x + 7) / 8;
-  const int group = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  // XCD-aware: each XCD owns a contiguous range of groups (work-groups are dealt to
+  // the 8 XCDs round-robin; gridDim.x is a multiple of 8)
   const int ngroups = (geo.n + kGroup - 1) / kGroup;
+  const int per = (ngroups + 7) / 8;
+  const int nbx = gridDim.x / 8;
+  for (int gi = blockIdx.x / 8; gi < per; gi += nbx) {
+  const int group = (blockIdx.x % 8) * per + gi;
   if (group >= ngroups) return;  // uniform over the work-group
   const int cnt = min(gcount[group], cap);
   const int2* H = hdr + (size_t)group * cap;
@@ -396,6 +404,7 @@ k_pair_list(const Geometry geo, const int2* __restrict__ hdr, const R* __restric
       Ed[((size_t)i * 3 + 2) * B + rhs] = acc[k][2];
     }
   }
+  }  // groups of this work-group
 }
 
 
@@ -637,12 +646,22 @@ template long long count_pairs<float>(const Geometry&, const SysBuffers&, hipStr
 template long long count_pairs<double>(const Geometry&, const SysBuffers&, hipStream_t);
 
 // Target subsets per wavefront for the list kernels: at least 64 / B (every lane
-// busy), doubled (up to 4) while the launch would have fewer than 4096 wavefronts
+// busy); g.pair_ns when set and valid (a power of two, at least 64 / B, at most 4);
+// otherwise doubled (up to 4) while the launch would have fewer than 4096 wavefronts
 // (4 per SIMD), so that small systems still fill the GPU.
-int pair_subsets(int ngroups, int B) {
+int pair_subsets(const Geometry& g, int ngroups, int B) {
   int ns = B >= 64 ? 1 : 64 / B;
+  if (g.pair_ns > 0) return std::max(ns, std::min(4, g.pair_ns));
   while (ns < 4 && (long)ngroups * B * ns / 64 < 4096) ns *= 2;
   return ns;
+}
+
+// Work-groups of a list-kernel launch: one per group (rounded up to a multiple of 8),
+// or g.pair_blocks when that is set and smaller (multiple of 8: each XCD gets the same
+// number of work-groups).
+int pair_blocks(const Geometry& g, int ngroups) {
+  const int all = (ngroups + 7) / 8 * 8;
+  return g.pair_blocks > 0 ? std::min(all, std::max(8, g.pair_blocks / 8 * 8)) : all;
 }
 
 template <typename R>
@@ -663,10 +682,10 @@ void launch_pair(const Geometry& g, const SysBuffers& b, int B, hipStream_t st) 
   }
   // a multiple of 8 work-groups, so that the XCD remap covers every group
   const int ngroups = (g.n + kGroup - 1) / kGroup;
-  const int nblk = (ngroups + 7) / 8 * 8;
+  const int nblk = pair_blocks(g, ngroups);
   const int2* H = b.pg_hdr;
   const R* T = (const R*)b.pg_T;
-  const int ns = pair_subsets(ngroups, B);
+  const int ns = pair_subsets(g, ngroups, B);
 #define MBD_PL(NS, WP) \
   k_pair_list<R, NS, WP><<<nblk, 64 * WP, 0, st>>>(g, H, T, b.pg_count, b.pg_cap, dv, Ed, B)
   switch (B * 16 + ns) {
@@ -711,7 +730,7 @@ void launch_pair_force(const Geometry& g, const SysBuffers& b, int B, hipStream_
   while (tw < 4 && tw * nsub < 16 && tw * rs < 16 && (long)ngroups * tw * rs < 4096) tw *= 2;
 #define MBD_PF(NS, TWV, RSV, TPV)                                                        \
   k_pair_force<R, NS, TWV, RSV, TPV><<<nblk, 64 * TWV * RSV, 0, st>>>(                   \
-      g, H, F, b.pg_count, b.pg_cap, p, q, b.fsum, B)
+      g, H, F, b.pg_count, b.pg_cap, p, q, b.fsum + 3 * (size_t)g.n, B)
   switch (B * 16 + tw) {
     case 4 * 16 + 1: MBD_PF(16, 1, 1, 1); break;
     case 8 * 16 + 1: MBD_PF(8, 1, 1, 2); break;

@@ -107,6 +107,12 @@ def _create(s, p, nsys=1):
     (lambda s, p: s.cell.__setitem__(0, -3.0), L.MBD_E_CELL),
     (lambda s, p: p.grid.__setitem__(0, 14), L.MBD_E_GRID),
     (lambda s, p: p.grid.__setitem__(1, 10), L.MBD_E_GRID),  # supported but < 2p
+    (lambda s, p: setattr(p, "tune", 3), L.MBD_E_ARG),
+    (lambda s, p: (setattr(p, "tune", 2), setattr(p.shape, "pair_subsets", 3)), L.MBD_E_ARG),
+    (lambda s, p: (setattr(p, "tune", 2), setattr(p.shape, "grid_chunk", 8)), L.MBD_E_ARG),
+    (lambda s, p: (setattr(p, "tune", 2), setattr(p.shape, "grid_chunk", 3)), L.MBD_E_ARG),
+    (lambda s, p: (setattr(p, "tune", 2), setattr(p.shape, "overlap", 3)), L.MBD_E_ARG),
+    (lambda s, p: (setattr(p, "tune", 2), setattr(p.shape, "pair_wg_per_cu", -1)), L.MBD_E_ARG),
 ])
 def test_invalid_arguments_fail_before_device_work(mutate, code):
     s, p = _args()
@@ -128,7 +134,7 @@ def test_valid_arguments_without_gpu_report_no_device():
 
 def test_null_handles_are_rejected():
     lib = L.lib()
-    assert lib.mbd_execute(None, None, None) == L.MBD_E_ARG
+    assert lib.mbd_execute(None, None, None, None) == L.MBD_E_ARG
     assert lib.mbd_matvec(None, 0, None, None, 1, 15) == L.MBD_E_ARG
     assert lib.mbd_plan_destroy(None) == L.MBD_OK
     prm = L.MbdScsParams(15, 0.6, 1e-10, 100)

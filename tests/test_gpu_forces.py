@@ -2,9 +2,10 @@
 Lanczos recurrence on the GPU) against automatic differentiation of the oracle's
 estimator with the same probes, and against central differences of the GPU energy.
 
-Tolerances: float64 path 1e-7 of the largest force component (rounding of the
-reverse sweep over m steps; the oracle differentiates the same definition);
-mixed path 2e-4 (float32 bilinear force terms, summed over R m right-hand sides)."""
+Tolerances, element-wise as a fraction of the largest force component: float64 path
+1e-7 (rounding of the reverse sweep over m steps; the oracle differentiates the same
+definition); mixed path 1e-5 (float32 grids, pair kernel and bilinear force terms,
+summed over R m right-hand sides in float64)."""
 import numpy as np
 import pytest
 import torch
@@ -54,8 +55,9 @@ def test_forces_fp64_match_oracle(tiny, block):
     e_ref, f_ref = _oracle_forces(tiny, plan, R, m)
     assert float(e[0]) == pytest.approx(e_ref, rel=1e-9)
     f = f.cpu()
-    err = float((f - f_ref).abs().max())
-    assert err <= 1e-7 * float(f_ref.abs().max()), err
+    err = float((f - f_ref).abs().max()) / float(f_ref.abs().max())
+    print(f"fp64 forces, block {block}: {err:.2e} of max |F|")
+    assert err <= 1e-7, err
 
 
 @pytest.mark.parametrize("block", [16, 64, 128])
@@ -67,8 +69,9 @@ def test_forces_mixed_match_oracle(tiny, block):
     plan.check()
     e_ref, f_ref = _oracle_forces(tiny, plan, R, m)
     assert float(e[0]) == pytest.approx(e_ref, rel=1e-5)
-    err = float((f.cpu() - f_ref).abs().max())
-    assert err <= 2e-4 * float(f_ref.abs().max()), err
+    err = float((f.cpu() - f_ref).abs().max()) / float(f_ref.abs().max())
+    print(f"mixed forces, block {block}: {err:.2e} of max |F|")
+    assert err <= 1e-5, err
 
 
 def test_forces_match_finite_differences_of_gpu_energy(tiny):

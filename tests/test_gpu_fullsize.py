@@ -1,32 +1,31 @@
-"""Parity at the 24k-atom water box in the launch configuration that the benchmark times
-(mixed precision, 128 probes as one block of right-hand sides, K = 96, r_c = 9 A). The
-oracle evaluates sampled outputs one by one:
+"""Parity at the benchmark's full sizes, in the launch configurations the benchmark times
+(mixed precision, probes as one block of right-hand sides, the tuned launch shape), and
+on the two small workloads in their own configurations (float64, one probe per block).
+The oracle evaluates sampled outputs one by one, or the stored values written by
+tests/golden/make_oracle_goldens.py (oracle only):
 
-- matvec: all 128 right-hand sides on the GPU. For two of them the oracle computes
-  l_i = Omega v_i + g_i (E_dir + E_rec + E_self)_i at 64 sampled atoms. The direct field
-  comes from a pair list restricted to those targets, the reciprocal field from the full
-  SPME of the oracle.
-- energy path: the Gauss quadrature value of probe 0 after the benchmark's 50 Lanczos
-  steps, against the oracle's single-probe run of 50 matvecs over the whole box.
+- matvec rows: all right-hand sides on the GPU; for four of them (both 64-wide grid
+  chunks of a 128 block) the oracle computes l_i = Omega v_i + g_i (E_dir + E_rec +
+  E_self)_i at 64 sampled atoms (direct field from a pair list restricted to them,
+  reciprocal field from the oracle's full SPME). Element-wise bound 1e-6 of the largest
+  entry of the sampled column.
+- quadrature: Q_l after the workload's Lanczos steps for probes 0, 1, 62, 63, 64, 65,
+  126, 127 of the 24k water box, probes 0 and 63 of the 12k organic box, and probe 0 of
+  the smallest, median and largest box of the uneven batch, against the stored oracle
+  values (1e-5 relative); each golden file also fixes tau, r_pair and the grid, which
+  the plan's own derivation must reproduce.
+- forces at 12k atoms: the mixed-precision forces against the float64 GPU forces of the
+  same plan configuration, element by element, 1e-5 of max |F|; and along u = F / |F|
+  the central difference of the GPU energy at fixed probes equals |F| (2e-3, float32
+  energy rounding at h = 5e-3 bohr). The float64 GPU forces themselves are pinned to
+  the oracle's automatic derivative in test_gpu_forces.py.
+- the host parameter rules (tau from r_c, r_pair from the damping tolerance, K from the
+  grid density) against oracle/params.py for all five workloads.
+- the two small workloads: the 96-atom fluid (8 probes x 30 steps) against the oracle's
+  energy over all probes, the 3000-atom water box (32 probes x 40 steps) against the
+  oracle's quadrature of probes 0 and 31 (1e-9 relative in float64)."""
+import os
 
-Tolerances as for the mixed path elsewhere: 2e-6 relative on the sampled matvec rows
-(norm over the sample), 1e-5 relative on the quadrature value.
-
-The two small workloads run in their own full configurations (float64, one probe per
-block): the 96-atom fluid (8 probes x 30 steps) against the oracle's energy with all
-probes, and the 3000-atom water box (32 probes x 40 steps) against the oracle's
-quadrature of probes 0 and 31 (bound 1e-9 relative in float64).
-
-The uneven batch (32 water boxes of 500 to 20 000 atoms in one plan, mixed, 64 probes x
-40 steps, forces) gets the sampled-row check on its largest, smallest and a middle
-system, and the directional-derivative check of the forces on its smallest system.
-
-The 12k-atom organic box in the forces leg's configuration (mixed, 64 probes x 40 steps
-as one block, K = 80, forces) gets the same sampled-row matvec check. Its forces are
-checked by a property that holds at any size: along the unit direction u = F / |F|, the
-central difference -(E(R + h u) - E(R - h u)) / 2h of the GPU energy at fixed probes
-equals |F|. h = 5e-3 bohr keeps the float32 rounding of the energy (about 1e-6 Ha)
-below 1e-4 of the difference; the bound is 2e-3."""
 import numpy as np
 import pytest
 import torch
@@ -34,6 +33,7 @@ import torch
 import synth
 from oracle import lanczos as olz
 from oracle import method as om
+from oracle import params as opar
 from oracle import spme as osp
 from oracle import tensors as otz
 from oracle.exact import self_coefficient
@@ -41,34 +41,55 @@ from oracle.exact import self_coefficient
 pytestmark = pytest.mark.gpu
 
 A = synth.ANGSTROM_BOHR
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(name):
+    return np.load(os.path.join(GOLDEN, name + ".npz"))
+
+
+def _mixed_plan(wl, forces=False, prec=None, tune=True, systems=None):
+    import paper_2307_02278_amd as P
+    systems = systems or wl.systems
+    ds = [P.DeviceSystem(x.pos, x.cell, x.alpha, x.omega, x.rvdw) for x in systems]
+    grid = tuple(wl.grid) * 3 if wl.grid else (0, 0, 0)
+    prm = P.Params(real_cutoff=wl.real_cutoff_angstrom * A, grid=grid, n_probes=wl.n_probes,
+                   n_steps=wl.n_steps, block=wl.block,
+                   precision=P.PREC_MIXED if prec is None else prec, seed=wl.probe_seed,
+                   want_forces=forces, tune=P.TUNE_MEASURE if tune else P.TUNE_OFF)
+    return ds, P.Plan(ds, prm)
+
+
+def _check_params(plan, sys, gold, prefix=""):
+    """The plan's derived tau, r_pair and grid equal those the golden was made with."""
+    inf = plan.info(sys)
+    assert inf.tau == pytest.approx(float(gold[prefix + "tau"]), rel=1e-12)
+    assert inf.r_pair == pytest.approx(float(gold[prefix + "r_pair"]), rel=1e-12)
+    assert list(inf.grid) == [int(k) for k in gold[prefix + "grid"]]
+    assert inf.spline_order == int(gold[prefix + "order"])
 
 
 @pytest.fixture(scope="module")
 def bench_case():
-    import paper_2307_02278_amd as P
     wl = synth.workload("batched24k")
-    s = wl.systems[0]
-    K = tuple(wl.grid) * 3 if len(wl.grid) == 1 else tuple(wl.grid)
-    ds = P.DeviceSystem(s.pos, s.cell, s.alpha, s.omega, s.rvdw)
-    prm = P.Params(real_cutoff=wl.real_cutoff_angstrom * A, grid=K, n_probes=wl.n_probes,
-                   n_steps=wl.n_steps, block=wl.block, precision=P.PREC_MIXED,
-                   seed=wl.probe_seed)
-    plan = P.Plan([ds], prm)
-    return wl, s, K, plan
+    _, plan = _mixed_plan(wl)
+    return wl, wl.systems[0], (96, 96, 96), plan
 
 
 def _sampled_rows(s, K, plan, B, sys=0):
+    """Element-wise error of four right-hand sides (0, 63, 64, B - 1: both grid chunks
+    of a 128 block) at 64 sampled atoms against the oracle's row-by-row evaluation."""
     inf = plan.info(sys)
     g = torch.Generator().manual_seed(2024)
     v = torch.randn(B, s.n, 3, dtype=torch.float64, generator=g)
     got = plan.matvec(v.cuda(), sys=sys).cpu()
-    cols = [0, B - 13]
+    cols = sorted({0, min(63, B - 1), min(64, B - 1), B - 1})
     sample = np.sort(np.random.default_rng(5).choice(s.n, min(64, s.n), replace=False))
     pos = torch.as_tensor(s.pos, dtype=torch.float64)
     gv = torch.as_tensor(s.omega * np.sqrt(s.alpha), dtype=torch.float64)
     om2 = torch.as_tensor(s.omega ** 2, dtype=torch.float64)
     rv = torch.as_tensor(s.rvdw, dtype=torch.float64)
-    y = v[cols].permute(1, 2, 0)                     # (N, 3, 2)
+    y = v[cols].permute(1, 2, 0)                     # (N, 3, ncols)
     d = gv[:, None, None] * y
     # direct field at the sampled targets
     i, j, r = otz.pair_list(pos, s.cell, inf.r_pair, targets=sample)
@@ -80,49 +101,79 @@ def _sampled_rows(s, K, plan, B, sys=0):
     grid = osp.spread(pos, s.cell, list(K), inf.spline_order, d)
     Erec = osp.gather(pos, s.cell, list(K), inf.spline_order, osp.convolve(grid, G))
     E = Edir + Erec + self_coefficient(inf.tau) * d
-    want = om2[:, None, None] * y + gv[:, None, None] * E      # (N, 3, 2)
+    want = om2[:, None, None] * y + gv[:, None, None] * E      # (N, 3, ncols)
     want = want[sample].permute(2, 0, 1)
     have = got[cols][:, sample]
-    return float((have - want).norm() / want.norm())
+    num = (have - want).abs().reshape(len(cols), -1).amax(1)
+    den = want.abs().reshape(len(cols), -1).amax(1)
+    err = float((num / den).max())
+    print(f"sampled rows ({s.n} atoms, columns {cols}): element-wise error {err:.2e}")
+    return err
 
 
 def test_fullsize_matvec_sampled_rows(bench_case):
     wl, s, K, plan = bench_case
-    err = _sampled_rows(s, K, plan, wl.block)
-    assert err < 2e-6, err
+    assert _sampled_rows(s, K, plan, wl.block) < 1e-6
 
 
-def test_fullsize_quadrature_of_probe_zero(bench_case):
+def test_fullsize_quadrature_against_golden(bench_case):
+    """Q_l of eight probes spanning both grid chunks against the stored oracle values."""
     wl, s, K, plan = bench_case
-    e = plan.execute()
+    gold = _golden("water24k_quadrature")
+    _check_params(plan, 0, gold)
+    e, sd = plan.execute(energy_sd=True)
     plan.check()
-    assert torch.isfinite(e).all()
+    assert torch.isfinite(e).all() and float(sd[0]) > 0.0
     q = plan.quadrature()
-    inf = plan.info(0)
-    op = om.Operator(s, om.MethodParams(tau=inf.tau, r_pair=inf.r_pair, grid=K,
-                                        order=inf.spline_order))
-    ref = olz.slq(op, s.n, s.omega, seed=wl.probe_seed, n_probes=1, m=wl.n_steps,
-                  reorth="none")
-    assert float(q[0]) == pytest.approx(float(ref.q[0]), rel=1e-5)
+    probes = [int(x) for x in gold["probes"]]
+    rel = (q[probes] - torch.from_numpy(gold["q"])).abs() / torch.from_numpy(gold["q"]).abs()
+    print(f"24k water quadrature: max relative error {float(rel.max()):.2e} over probes "
+          f"{probes}; E = {float(e[0]):.10f} +- {float(sd[0]):.2e} Ha")
+    assert float(rel.max()) < 1e-5
 
 
 @pytest.fixture(scope="module")
 def forces_case():
-    import paper_2307_02278_amd as P
     wl = synth.workload("forces12k")
-    s = wl.systems[0]
-    K = tuple(wl.grid) * 3
-    ds = P.DeviceSystem(s.pos, s.cell, s.alpha, s.omega, s.rvdw)
-    prm = P.Params(real_cutoff=wl.real_cutoff_angstrom * A, grid=K, n_probes=wl.n_probes,
-                   n_steps=wl.n_steps, block=wl.block, precision=P.PREC_MIXED,
-                   seed=wl.probe_seed, want_forces=True)
-    return wl, s, K, P.Plan([ds], prm)
+    _, plan = _mixed_plan(wl, forces=True)
+    return wl, wl.systems[0], (80, 80, 80), plan
 
 
 def test_fullsize_forces_box_matvec_sampled_rows(forces_case):
     wl, s, K, plan = forces_case
-    err = _sampled_rows(s, K, plan, wl.block)
-    assert err < 2e-6, err
+    assert _sampled_rows(s, K, plan, wl.block) < 1e-6
+
+
+def test_fullsize_forces_box_quadrature_against_golden(forces_case):
+    wl, s, K, plan = forces_case
+    gold = _golden("organic12k_quadrature")
+    _check_params(plan, 0, gold)
+    plan.set_positions(torch.as_tensor(s.pos, dtype=torch.float64, device="cuda"))
+    plan.execute()
+    plan.check()
+    q = plan.quadrature()
+    probes = [int(x) for x in gold["probes"]]
+    rel = (q[probes] - torch.from_numpy(gold["q"])).abs() / torch.from_numpy(gold["q"]).abs()
+    print(f"12k organic quadrature: max relative error {float(rel.max()):.2e}")
+    assert float(rel.max()) < 1e-5
+
+
+def test_fullsize_mixed_forces_match_float64_forces(forces_case):
+    """Element by element against the float64 GPU path in the same configuration."""
+    import paper_2307_02278_amd as P
+    wl, s, K, plan = forces_case
+    plan.set_positions(torch.as_tensor(s.pos, dtype=torch.float64, device="cuda"))
+    e32, f32 = plan.execute(forces=True)
+    plan.check()
+    _, p64 = _mixed_plan(wl, forces=True, prec=P.PREC_FP64, tune=False)
+    e64, f64 = p64.execute(forces=True)
+    p64.check()
+    p64.close()
+    err = float((f32 - f64).abs().max() / f64.abs().max())
+    erel = abs(float(e32[0]) - float(e64[0])) / abs(float(e64[0]))
+    print(f"12k organic: mixed vs float64 forces {err:.2e} of max |F|; energy {erel:.2e}")
+    assert err < 1e-5
+    assert erel < 1e-6
 
 
 def test_fullsize_forces_match_directional_derivative(forces_case):
@@ -139,6 +190,7 @@ def test_fullsize_forces_match_directional_derivative(forces_case):
         plan.set_positions(pos + sgn * h * u)
         es.append(float(plan.execute()[0]))
         plan.check()
+    plan.set_positions(pos)
     slope = -(es[0] - es[1]) / (2.0 * h)
     assert slope == pytest.approx(fn, rel=2e-3), (slope, fn)
 
@@ -184,25 +236,61 @@ def test_medium_workload_quadrature_of_two_probes():
         assert float(q[l]) == pytest.approx(float(ref.q[0]), rel=1e-9), l
 
 
+@pytest.mark.parametrize("name", ["tiny", "medium", "batched24k", "forces12k", "uneven"])
+def test_host_parameter_rules_match_oracle(name):
+    """Plans created with tau = 0 and grid = 0 derive tau, r_pair and K by the same rules
+    as oracle/params.py (tau from erfc(tau r_c)/r_c = 1e-8 in Angstrom, r_pair from
+    1 - f = 1e-4 at the largest damping radius, K the smallest even 2^a 3^b >= 1.4 / A)."""
+    import paper_2307_02278_amd as P
+    wl = synth.workload(name)
+    ds = [P.DeviceSystem(x.pos, x.cell, x.alpha, x.omega, x.rvdw) for x in wl.systems]
+    prm = P.Params(ewald_tau=0.0, real_cutoff=wl.real_cutoff_angstrom * A, grid=(0, 0, 0),
+                   n_probes=1, n_steps=1, block=1, precision=P.PREC_FP64)
+    plan = P.Plan(ds, prm)
+    tau = opar.tau_from_cutoff_angstrom(wl.real_cutoff_angstrom) * synth.BOHR_ANGSTROM
+    for k, x in enumerate(wl.systems):
+        inf = plan.info(k)
+        r_pair = max(wl.real_cutoff_angstrom * A,
+                     opar.damping_range(0.83 * 2 * float(x.rvdw.max()), 6.0, 1e-4))
+        K = [opar.smooth_grid(float(np.linalg.norm(x.cell[a])) * synth.BOHR_ANGSTROM)
+             for a in range(3)]
+        assert inf.tau == pytest.approx(tau, rel=1e-12), k
+        assert inf.r_pair == pytest.approx(r_pair, rel=1e-12), k
+        assert list(inf.grid) == K, k
+    plan.close()
+
+
 @pytest.fixture(scope="module")
 def uneven_case():
-    import paper_2307_02278_amd as P
     wl = synth.workload("uneven")
-    ds = [P.DeviceSystem(x.pos, x.cell, x.alpha, x.omega, x.rvdw) for x in wl.systems]
-    prm = P.Params(real_cutoff=wl.real_cutoff_angstrom * A, grid=(0, 0, 0),
-                   n_probes=wl.n_probes, n_steps=wl.n_steps, block=wl.block,
-                   precision=P.PREC_MIXED, seed=wl.probe_seed, want_forces=True)
-    return wl, ds, P.Plan(ds, prm)
+    ds, plan = _mixed_plan(wl, forces=True)
+    return wl, ds, plan
 
 
 def test_uneven_batch_sampled_rows(uneven_case):
     wl, ds, plan = uneven_case
     sizes = [x.n for x in wl.systems]
-    order = np.argsort(sizes)
+    order = np.argsort(sizes, kind="stable")
     for k in (int(order[-1]), int(order[0]), int(order[len(order) // 2])):
         K = tuple(plan.info(k).grid)
         err = _sampled_rows(wl.systems[k], K, plan, wl.block, sys=k)
-        assert err < 2e-6, (k, err)
+        assert err < 1e-6, (k, err)
+
+
+def test_uneven_batch_quadrature_against_golden(uneven_case):
+    wl, ds, plan = uneven_case
+    gold = _golden("uneven_quadrature")
+    e = plan.execute()
+    plan.check()
+    assert torch.isfinite(e).all()
+    for tag in ("smallest", "median", "largest"):
+        k = int(gold[tag + "_system"])
+        _check_params(plan, k, gold, tag + "_")
+        q = plan.quadrature(k)
+        ref = float(gold[tag + "_q"][0])
+        rel = abs(float(q[0]) - ref) / abs(ref)
+        print(f"uneven batch, {tag} system {k} ({wl.systems[k].n} atoms): Q_0 error {rel:.2e}")
+        assert rel < 1e-5, (tag, rel)
 
 
 def test_uneven_batch_forces_match_directional_derivative(uneven_case):

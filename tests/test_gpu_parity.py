@@ -1,8 +1,10 @@
 """GPU parity: the HIP path through the C ABI against the CPU oracle on the same
-seeded inputs. Tolerances: float64 path 1e-11 relative on matvecs (rounding of
-differently ordered sums over up to ~1e4 terms); mixed path (float32 SPME and
-pair kernel, float64 Lanczos) 2e-6 relative on matvecs and 1e-5 relative on
-E_MBD at fixed probes."""
+seeded inputs, element by element. A matvec error is, for each right-hand side,
+max |got - want| / max |want|, and the largest over the right-hand sides is bounded.
+Tolerances: float64 path 1e-11 (rounding of differently ordered sums over up to ~1e4
+terms); mixed path (float32 SPME and pair kernel, float64 Omega v, self term and
+Lanczos) 1e-6 on C v, the field parts alone at their float32 level (MIXED_TOL), and
+1e-5 relative on E_MBD at fixed probes."""
 import math
 
 import numpy as np
@@ -35,8 +37,19 @@ def _oracle_op(s, plan):
     return om.Operator(s, mp)
 
 
-def _rel(a, b):
-    return float((a - b).norm() / b.norm())
+def _err(got, want, label=""):
+    """Element-wise error of a block of vectors [nrhs][N][3]: the largest, over the
+    right-hand sides, of max |got - want| / max |want| within that right-hand side."""
+    num = (got - want).abs().reshape(got.shape[0], -1).amax(1)
+    den = want.abs().reshape(want.shape[0], -1).amax(1)
+    e = float((num / den).max())
+    print(f"element-wise error {label}: {e:.2e}")
+    return e
+
+
+# float32 grids and pair kernel: the whole C v to the 1e-6 bound; single parts of the
+# field (no Omega v in them) to their own float32 rounding level
+MIXED_TOL = {1: 1e-13, 2: 1e-5, 4: 1e-5, 8: 1e-13, 15: 1e-6}
 
 
 @pytest.fixture(scope="module")
@@ -60,7 +73,7 @@ def test_matvec_fp64_components(tiny, rhs4, comp, name):
     op = _oracle_op(tiny, plan)
     got = plan.matvec(rhs4.cuda(), components=comp).cpu()
     want = op(rhs4.permute(1, 2, 0), comp).permute(2, 0, 1)
-    assert _rel(got, want) < 1e-11, name
+    assert _err(got, want, name) < 1e-11, name
 
 
 @pytest.mark.parametrize("comp,name", COMPONENTS)
@@ -70,8 +83,7 @@ def test_matvec_mixed_components(tiny, rhs4, comp, name):
     op = _oracle_op(tiny, plan)
     got = plan.matvec(rhs4.cuda(), components=comp).cpu()
     want = op(rhs4.permute(1, 2, 0), comp).permute(2, 0, 1)
-    tol = 2e-6 if comp in (15, 1) else 1e-5
-    assert _rel(got, want) < tol, name
+    assert _err(got, want, name) < MIXED_TOL[comp], name
 
 
 @pytest.mark.parametrize("block", [1, 2, 16, 32, 64])
@@ -85,7 +97,7 @@ def test_matvec_block_layouts_agree(tiny, block):
     v = torch.randn(n, tiny.n, 3, dtype=torch.float64, generator=g)
     got = plan.matvec(v.cuda()).cpu()
     want = op(v.permute(1, 2, 0)).permute(2, 0, 1)
-    assert _rel(got, want) < 1e-11
+    assert _err(got, want, f"block {block}") < 1e-11
 
 
 @pytest.mark.parametrize("block", [16, 32, 64, 128, 256])
@@ -101,7 +113,7 @@ def test_matvec_mixed_wide_blocks(tiny, block, comp):
     v = torch.randn(block, tiny.n, 3, dtype=torch.float64, generator=g)
     got = plan.matvec(v.cuda(), components=comp).cpu()
     want = op(v.permute(1, 2, 0), comp).permute(2, 0, 1)
-    assert _rel(got, want) < (2e-6 if comp == 15 else 1e-5)
+    assert _err(got, want, f"block {block} comp {comp}") < MIXED_TOL[comp]
 
 
 @pytest.fixture(scope="module")
@@ -109,7 +121,7 @@ def water3k():
     return synth.workload("medium").systems[0]
 
 
-@pytest.mark.parametrize("prec,block,tol", [(0, 2, 1e-11), (1, 64, 2e-6)])
+@pytest.mark.parametrize("prec,block,tol", [(0, 2, 1e-11), (1, 64, 1e-6)])
 def test_matvec_water_3000(water3k, prec, block, tol):
     """Medium water box (K=48, r_c=7 A): several cells per axis, many tiles and groups."""
     s = water3k
@@ -120,7 +132,7 @@ def test_matvec_water_3000(water3k, prec, block, tol):
     v = torch.randn(n, s.n, 3, dtype=torch.float64, generator=g)
     got = plan.matvec(v.cuda()).cpu()
     want = op(v.permute(1, 2, 0)).permute(2, 0, 1)
-    assert _rel(got, want) < tol
+    assert _err(got, want, f"water3000 prec {prec}") < tol
 
 
 def test_matvec_noncubic_grid_radix_3_5():
@@ -133,10 +145,11 @@ def test_matvec_noncubic_grid_radix_3_5():
     plan, _ = _plan(s, P.PREC_FP64, 2, grid=(20, 24, 30), tau_ang=0.35, rc_ang=13.0)
     op = _oracle_op(s, plan)
     v = torch.randn(2, s.n, 3, dtype=torch.float64, generator=torch.Generator().manual_seed(3))
-    assert _rel(plan.matvec(v.cuda()).cpu(), op(v.permute(1, 2, 0)).permute(2, 0, 1)) < 1e-11
+    assert _err(plan.matvec(v.cuda()).cpu(), op(v.permute(1, 2, 0)).permute(2, 0, 1),
+                "ortho fp64") < 1e-11
 
 
-@pytest.mark.parametrize("grid", [(18, 24, 30), (30, 20, 24)])
+@pytest.mark.parametrize("grid", [(18, 24, 30), (30, 20, 24), (50, 24, 30), (90, 20, 24)])
 @pytest.mark.parametrize("comp", [4, 15])
 def test_matvec_mixed_noncubic_odd_half_lengths(grid, comp):
     """Float32 grid path with 16 right-hand sides on unequal axes whose x length K1 = 18 or
@@ -152,7 +165,7 @@ def test_matvec_mixed_noncubic_odd_half_lengths(grid, comp):
     v = torch.randn(16, s.n, 3, dtype=torch.float64, generator=torch.Generator().manual_seed(5))
     got = plan.matvec(v.cuda(), components=comp).cpu()
     want = op(v.permute(1, 2, 0), comp).permute(2, 0, 1)
-    assert _rel(got, want) < (2e-6 if comp == 15 else 1e-5)
+    assert _err(got, want, f"grid {grid} comp {comp}") < MIXED_TOL[comp]
 
 
 def _compare_lanczos(s, prec, block, R, m, tol_q, tol_e, **kw):
@@ -236,7 +249,7 @@ def test_set_positions_rebuilds_pair_list():
     v = torch.randn(3, s1.n, 3, dtype=torch.float64, generator=torch.Generator().manual_seed(9))
     got = plan.matvec(v.cuda()).cpu()
     plan.check()
-    assert _rel(got, op(v.permute(1, 2, 0)).permute(2, 0, 1)) < 2e-6
+    assert _err(got, op(v.permute(1, 2, 0)).permute(2, 0, 1), "moved") < MIXED_TOL[15]
 
 
 def test_pair_list_overflow_is_reported():
@@ -278,3 +291,31 @@ def test_uneven_batch_runs_concurrently_and_matches_oracle():
             order=plan.info(k).spline_order, beta=0.83, d=6.0))
         ref = olz.slq(op, x.n, x.omega, seed=12345, n_probes=R, m=m, system=k)
         assert float(e[k]) == pytest.approx(float(ref.energy), rel=1e-9, abs=1e-14), k
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_energy_sd_matches_oracle_spread(tiny, graph):
+    """sd(E) = 1/2 (3N) s_Q / sqrt(R) from the sample spread s_Q of the per-probe
+    quadrature values (eq. hutch averages R independent samples), against the same
+    formula applied to the oracle's per-probe values; one probe gives NaN."""
+    import paper_2307_02278_amd as P
+    R, m = 8, 30
+    ds = P.DeviceSystem(tiny.pos, tiny.cell, tiny.alpha, tiny.omega, tiny.rvdw)
+    prm = P.Params(ewald_tau=0.35 * synth.BOHR_ANGSTROM, real_cutoff=13.0 * A,
+                   grid=(16, 16, 16), n_probes=R, n_steps=m, block=8,
+                   precision=P.PREC_FP64, graph=graph)
+    plan = P.Plan([ds], prm)
+    for _ in range(2 if graph else 1):
+        e, sd = plan.execute(energy_sd=True)
+    plan.check()
+    op = _oracle_op(tiny, plan)
+    ref = olz.slq(op, tiny.n, tiny.omega, seed=12345, n_probes=R, m=m, reorth="full")
+    want = 0.5 * 3 * tiny.n * float(ref.q.std(unbiased=True)) / math.sqrt(R)
+    print(f"sd(E) gpu {float(sd[0]):.6e} oracle {want:.6e}; E {float(e[0]):.8e}")
+    assert float(sd[0]) == pytest.approx(want, rel=1e-8)
+    one = P.Plan([ds], P.Params(ewald_tau=0.35 * synth.BOHR_ANGSTROM, real_cutoff=13.0 * A,
+                                grid=(16, 16, 16), n_probes=1, n_steps=5, block=1,
+                                precision=P.PREC_FP64, graph=graph))
+    _, sd1 = one.execute(energy_sd=True)
+    one.check()
+    assert math.isnan(float(sd1[0]))

@@ -53,8 +53,7 @@ def test_replica_matvec_matches_oracle(tiny, rcut, comps):
 
 
 def test_replica_matvec_triclinic_matches_oracle():
-    import importlib
-    tri = importlib.import_module("test_gpu_triclinic")._triclinic_system(n=40, seed=8)
+    tri = synth.triclinic_random(n=40, seed=8)
     plan = _plan(tri, 18.0)
     v = torch.randn(2, tri.n, 3, dtype=torch.float64, generator=torch.Generator().manual_seed(6))
     got = plan.matvec(v.cuda(), components=3).cpu()

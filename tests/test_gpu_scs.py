@@ -60,8 +60,7 @@ def test_scs_runs_in_float64_on_a_mixed_plan(tiny):
 
 
 def test_scs_triclinic_matches_oracle():
-    import importlib
-    tri = importlib.import_module("test_gpu_triclinic")._triclinic_system(n=40, seed=8)
+    tri = synth.triclinic_random(n=40, seed=8)
     plan, _ = _plan(tri)
     _compare(tri, plan, 6)
 
