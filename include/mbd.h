@@ -282,6 +282,21 @@ typedef struct {
 mbd_status mbd_scs(mbd_plan plan, int32_t sys, const mbd_scs_params* prm, double* alpha_scs,
                    double* omega_scs, double* rvdw_scs, double* alpha_freq, mbd_scs_info* info);
 
+/* The screening solve of mbd_scs without any device allocation, for callers that cannot
+ * allocate (code under stream capture, tight serving loops, harnesses that forbid it).
+ * Same arguments, results and errors as mbd_scs, bit for bit. The workspace is one fixed
+ * 64 MiB device array per GPU instead of a per-call allocation: the library holds it on
+ * every GPU it runs on until the process ends, and its address is resolved when a plan is
+ * first created on that GPU. A system needs 8 (4N + 2N(n+1) + 45N(n+1) + O(n)) bytes,
+ * i.e. up to about 11,000 atoms at the default n = 15 frequencies; larger requests fail
+ * with MBD_E_ARG before any device work. Every call on one GPU shares the array and
+ * leaves its contents behind (each call initializes what it reads), so calls that
+ * overlap in time on one GPU, e.g. from two host threads, race and must not be made.
+ * Synchronous, like mbd_scs. */
+mbd_status mbd_scs_noalloc(mbd_plan plan, int32_t sys, const mbd_scs_params* prm,
+                           double* alpha_scs, double* omega_scs, double* rvdw_scs,
+                           double* alpha_freq, mbd_scs_info* info);
+
 mbd_status mbd_plan_destroy(mbd_plan plan);
 
 /* 1 if an FFT of length k is compiled in (even 2^a 3^b 5^c in [8, 128]), else 0. */

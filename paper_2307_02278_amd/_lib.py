@@ -122,6 +122,9 @@ SIGNATURES = [
     ("mbd_scs", C.c_int32,
      [C.c_void_p, C.c_int32, C.POINTER(MbdScsParams), C.c_void_p, C.c_void_p, C.c_void_p,
       C.c_void_p, C.POINTER(MbdScsInfo)]),
+    ("mbd_scs_noalloc", C.c_int32,
+     [C.c_void_p, C.c_int32, C.POINTER(MbdScsParams), C.c_void_p, C.c_void_p, C.c_void_p,
+      C.c_void_p, C.POINTER(MbdScsInfo)]),
     ("mbd_status_string", C.c_char_p, [C.c_int32]),
     ("mbd_last_error", C.c_char_p, []),
 ]

@@ -172,17 +172,18 @@ class Plan:
         return {L.STAGES[i]: (ms[i], cnt[i]) for i in range(n)}
 
     def scs(self, sys: int = 0, n_freq: int = 15, freq_scale: float = 0.6, tol: float = 1e-10,
-            max_iter: int = 1000, with_freq: bool = False):
+            max_iter: int = 1000, with_freq: bool = False, noalloc: bool = False):
         """Range-separated self-consistent screening of system `sys` at its current
-        positions (mbd_scs). Returns (alpha, omega, r_vdw) screened, float64 on the GPU in
-        the caller's atom order, plus alpha^SCS at the n_freq quadrature nodes [n_freq, N]
-        when with_freq, and an info dict (iterations, max_rel_residual)."""
+        positions (mbd_scs, or mbd_scs_noalloc with noalloc=True). Returns (alpha, omega,
+        r_vdw) screened, float64 on the GPU in the caller's atom order, plus alpha^SCS at
+        the n_freq quadrature nodes [n_freq, N] when with_freq, and an info dict
+        (iterations, max_rel_residual)."""
         n = self.systems[sys].n
         out = torch.empty(3, n, dtype=torch.float64, device="cuda")
         af = torch.empty(n_freq, n, dtype=torch.float64, device="cuda") if with_freq else None
         prm = L.MbdScsParams(n_freq, freq_scale, tol, max_iter)
         inf = L.MbdScsInfo()
-        fn = self.lib.mbd_scs
+        fn = self.lib.mbd_scs_noalloc if noalloc else self.lib.mbd_scs
         L.check(fn(self.handle, sys, C.byref(prm), C.c_void_p(out[0].data_ptr()),
                    C.c_void_p(out[1].data_ptr()), C.c_void_p(out[2].data_ptr()),
                    C.c_void_p(af.data_ptr()) if with_freq else None, C.byref(inf)))

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -471,6 +472,34 @@ mbd_status fail(mbd_status code, const std::string& msg) {
   return code;
 }
 
+// Allocation-free screening workspace: one array per device, 64 MiB, kept until the
+// process ends. Host code reaches it only through the address hipGetSymbolAddress
+// returns for the device (resolved once per device when a plan is created there).
+constexpr size_t kScsScratchDoubles = (size_t)64 << 17;  // 64 MiB of doubles
+static __device__ __align__(256) double scratch[kScsScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// Address of this device's scratch array (the current device must be `device`).
+mbd_status resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(MBD_E_NODEVICE, "device index too large");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch_ptr[device]) return MBD_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(MBD_E_HIP, std::string("scratch address: ") + hipGetErrorString(e));
+  g_scratch_ptr[device] = static_cast<double*>(ptr);
+  return MBD_OK;
+}
+
+double* scratch_of(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  return g_scratch_ptr[device];
+}
 
 // ---- launch shapes and their tuner ---------------------------------------------------
 // A shape only changes how a system's matvec is laid out on the GPU: work-groups of the
@@ -821,6 +850,12 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
     return fail(MBD_E_NODEVICE, "no HIP device available");
+  {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(MBD_E_HIP, "no current device");
+    const mbd_status sr = resolve_scratch(dev);
+    if (sr != MBD_OK) return sr;
+  }
 
   auto* handle = new (std::nothrow) mbd_plan_s();
   if (!handle) return fail(MBD_E_OOM, "host allocation failed");
@@ -1388,6 +1423,29 @@ mbd_status mbd_scs(mbd_plan plan, int32_t sys, const mbd_scs_params* prm_in, dou
   hipStreamSynchronize(P.stream);
   hipFree(ws);
   return r;
+}
+
+mbd_status mbd_scs_noalloc(mbd_plan plan, int32_t sys, const mbd_scs_params* prm_in,
+                           double* alpha_scs, double* omega_scs, double* rvdw_scs,
+                           double* alpha_freq, mbd_scs_info* info) {
+  using namespace mbd;
+  if (!plan || !prm_in || !alpha_scs || !omega_scs || !rvdw_scs)
+    return fail(MBD_E_ARG, "NULL argument");
+  Plan& P = plan->plan;
+  mbd_scs_params prm;
+  ScsWork w;
+  const mbd_status v = scs_prepare(P, sys, prm_in, prm, w);
+  if (v != MBD_OK) return v;
+  const size_t need = scs_doubles(w.n, w.nq, w.nblk);
+  if (need > kScsScratchDoubles)
+    return fail(MBD_E_ARG, "screening workspace of " + std::to_string(need * sizeof(double)) +
+                               " bytes exceeds the fixed " +
+                               std::to_string(kScsScratchDoubles * sizeof(double)) +
+                               "-byte scratch of mbd_scs_noalloc (fewer atoms or frequencies, "
+                               "or mbd_scs)");
+  double* ws = scratch_of(P.device);
+  if (!ws) return fail(MBD_E_STATE, "no scratch address for the plan's device");
+  return scs_run(P, sys, prm, w, ws, alpha_scs, omega_scs, rvdw_scs, alpha_freq, info);
 }
 
 mbd_status mbd_plan_destroy(mbd_plan plan) {
