@@ -7,20 +7,23 @@ molecules at 1 g/cm^3, 62.09 A cube): device setup at the step's positions,
 (6400 probe-vector matvecs through the pair kernel and SPME on a 96^3 grid,
 order-6 B-splines, 9 A real-space cutoff), the tridiagonal quadrature and the
 energy sum. SPME and the pair kernel run in float32, the Lanczos recurrence,
-quadrature and energy in float64 ("mixed").
+quadrature and energy in float64 ("mixed"). The plan's launch shape is measured
+on the box at plan creation (outside the timed region) and replayed from a HIP graph.
 
 Prints one JSON line on stdout; progress goes to stderr.
-  metric  probe-vector SPME matvecs per second (batched, mixed precision)
-  extra   plain one-vector float64 rate on the same GPU, the speedup, per-stage
-          times, the roofline of the dominant kernel, the CPU oracle rate, and the
-          E_MBD + forces wall time of the 12k-atom organic box (K=80, 64 probes x 40
-          steps, mixed); with --uneven also of the batch of 32 water boxes of
-          log-uniform size (500..20000 atoms, 64 probes x 40 steps each).
+  value   probe-vector SPME matvecs per second (batched, mixed precision)
+  extra   E_MBD + forces wall time at the same box (median of graph replays), the
+          plain one-vector float64 rate on the same GPU and the speedup, per-stage
+          times, the dominant kernel's roofline, errors against stored oracle values,
+          the CPU oracle rate (all threads and one thread, CPU model), and the
+          E + F legs of the 12k-atom organic box and of the batch of 32 water boxes.
 """
 import argparse
 import json
 import math
 import os
+import statistics
+import subprocess
 import sys
 import time
 
@@ -29,22 +32,24 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 FMA lanes x 2 flop x 2.4 GHz (no packed FP32)
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+FP32_PEAK_TFLOPS = 157.3         # MI355X published FP32 vector peak (packed FMA)
+FP32_NONPACKED_TFLOPS = 78.6     # 256 CU x 64 FMA lanes x 2 flop x 2.4 GHz, no packed FP32
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Kernel that implements each timed stage at this workload (float, p = 6, 64-wide chunks).
-# Kernel instance behind each stage at the 24k workload (B = 128: the dispatch picks two
-# target subsets per wavefront and four wavefronts per group, as the kernel trace shows).
+# Kernel instance behind each stage at the 24k workload (float, p = 6, 64-wide chunks,
+# B = 128: the list kernel runs two target subsets per wavefront and four wavefronts
+# per group).
 STAGE_KERNEL = {
     "pair": "k_pair_list<float, 2, 4>", "spread": "k_spread<float, 6, 64>",
-    "fft_x": "k_fft_reg<96, 0>", "fft_y": "k_fft_reg<96, 1>", "fft_z_conv": "k_fft_reg<96, 2>",
-    "ifft_y": "k_fft_reg<96, 3>", "ifft_x": "k_fft_reg<96, 4>",
-    "gather": "k_gather_epilogue<float, 6, 64>",
+    "fft_x": "k_fft_x_real<96, true>", "fft_y": "k_fft_reg<96, 1>",
+    "fft_z_conv": "k_fft_reg<96, 2>", "ifft_y": "k_fft_reg<96, 3>",
+    "ifft_x": "k_fft_x_real<96, false>", "gather": "k_gather_epilogue<float, 6, 64>",
 }
 
 
@@ -84,53 +89,127 @@ def stage_bytes(stage, K, N, B):
     return None if per is None else per * B
 
 
-def energy_forces_leg(P, torch, synth, name, graph):
-    """E_MBD + forces wall time (set_positions + execute with forces) for one workload,
-    next to the energy-only time of the same plan; one warm-up run first."""
-    wl = synth.workload(name)
+def golden(name):
+    path = os.path.join(GOLDEN, name + ".npz")
+    return np.load(path) if os.path.exists(path) else None
+
+
+def quadrature_error(plan, gold, sys=0, prefix=""):
+    """Largest relative error of the plan's per-probe quadrature values against stored
+    oracle values (the probes the golden file lists)."""
+    if gold is None:
+        return None
+    q = plan.quadrature(sys).numpy()
+    probes = [int(x) for x in gold[prefix + "probes"]]
+    ref = gold[prefix + "q"]
+    return float(np.max(np.abs(q[probes] - ref) / np.abs(ref)))
+
+
+def median_ms(fn, reps, torch):
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        ts.append(1000.0 * (time.perf_counter() - t0))
+    return statistics.median(ts), out
+
+
+def plan_for(P, synth, wl, forces, graph, tune, precision=None, shape=None, systems=None):
     A = synth.ANGSTROM_BOHR
-    grid = tuple(wl.grid) * 3 if wl.grid and len(wl.grid) == 1 else (0, 0, 0)
-    ds = [P.DeviceSystem(x.pos, x.cell, x.alpha, x.omega, x.rvdw) for x in wl.systems]
+    systems = systems or wl.systems
+    ds = [P.DeviceSystem(x.pos, x.cell, x.alpha, x.omega, x.rvdw) for x in systems]
+    grid = tuple(wl.grid) * 3 if wl.grid else (0, 0, 0)
     prm = P.Params(real_cutoff=wl.real_cutoff_angstrom * A, grid=grid, n_probes=wl.n_probes,
-                   n_steps=wl.n_steps, block=wl.block, precision=P.PREC_MIXED,
-                   seed=wl.probe_seed, want_forces=True, graph=graph)
-    plan = P.Plan(ds, prm)
+                   n_steps=wl.n_steps, block=wl.block,
+                   precision=P.PREC_MIXED if precision is None else precision,
+                   seed=wl.probe_seed, want_forces=forces, graph=graph,
+                   tune=(P.TUNE_GIVEN if shape else (P.TUNE_MEASURE if tune else P.TUNE_OFF)),
+                   shape=shape)
+    return ds, P.Plan(ds, prm)
+
+
+def shape_of(P, plan, sys=0):
+    inf = plan.info(sys)
+    d = {k: int(getattr(inf.shape, k)) for k, _ in P.MbdShape._fields_}
+    d["source"] = P.SHAPE_SOURCES[inf.shape_source]
+    return d
+
+
+def energy_forces_leg(P, torch, synth, name, graph, reps, fp64_check=False, golden_name=None):
+    """E_MBD + forces wall time (set_positions + execute with forces) for one workload:
+    median of `reps` runs after a warm-up, next to the energy-only median of the same
+    plan; errors of the per-probe quadrature against stored oracle values; optionally
+    the largest force difference against the float64 GPU path."""
+    wl = synth.workload(name)
+    t0 = time.perf_counter()
+    ds, plan = plan_for(P, synth, wl, forces=True, graph=graph, tune=True)
+    t_plan = time.perf_counter() - t0
     pos = [d.pos.clone() for d in ds]
 
     def run(forces):
         for k, p in enumerate(pos):
             plan.set_positions(p, k)
-        return plan.execute(forces=forces)
+        return plan.execute(forces=forces, energy_sd=True)
 
     run(True)
     run(False)
     torch.cuda.synchronize()
     plan.check()
-    t0 = time.perf_counter()
-    e, f = run(True)
-    torch.cuda.synchronize()
-    t_ef = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    run(False)
-    torch.cuda.synchronize()
-    t_e = time.perf_counter() - t0
+    t_ef, (e, f, sd) = median_ms(lambda: run(True), reps, torch)
+    t_e, _ = median_ms(lambda: run(False), reps, torch)
     plan.check()
-    # per-stage times from one more (eager, event-timed) run
+    out = {"workload": name, "systems": len(wl.systems), "atoms": sum(x.n for x in wl.systems),
+           "probes": wl.n_probes, "lanczos_steps": wl.n_steps, "block": wl.block,
+           "execution": "hip_graph_replay" if graph else "eager", "replays": reps,
+           "energy_forces_ms": round(t_ef, 2), "energy_only_ms": round(t_e, 2),
+           "plan_create_s": round(t_plan, 2), "forces_finite": bool(torch.isfinite(f).all()),
+           "shape": shape_of(P, plan)}
+    if len(wl.systems) == 1:
+        out["energy_ha"] = float(e[0])
+        out["energy_sd_ha"] = float(sd[0])
+    gold = golden(golden_name) if golden_name else None
+    if gold is not None:
+        if "probes" in gold:
+            out["quadrature_rel_err_vs_oracle"] = quadrature_error(plan, gold)
+        else:
+            errs = [quadrature_error(plan, gold, int(gold[t + "_system"]), t + "_")
+                    for t in ("smallest", "median", "largest")]
+            out["quadrature_rel_err_vs_oracle"] = max(errs)
+        out["oracle_reference"] = f"tests/golden/{golden_name}.npz"
+    if fp64_check:
+        _, p64 = plan_for(P, synth, wl, forces=True, graph=False, tune=False,
+                          precision=P.PREC_FP64)
+        for k, p in enumerate(pos):
+            p64.set_positions(p, k)
+        e64, f64 = p64.execute(forces=True)
+        p64.check()
+        out["forces_max_err_vs_fp64_gpu"] = float((f - f64).abs().max() / f64.abs().max())
+        out["energy_rel_err_vs_fp64_gpu"] = float((e - e64).abs().max() / e64.abs().max())
+        p64.close()
+    # per-stage times from one more eager, event-timed run
     plan.stage_times()
     plan.set_timing(True)
     run(True)
     plan.set_timing(False)
-    stages = plan.stage_times()
-    n_atoms = sum(x.n for x in wl.systems)
-    ok = bool(torch.isfinite(f).all())
+    out["stage_ms"] = {k: round(v[0], 2) for k, v in plan.stage_times().items() if v[1] > 0}
     plan.close()
-    log(f"{name}: E+F {1000 * t_ef:.1f} ms, E only {1000 * t_e:.1f} ms")
-    return {"workload": name, "systems": len(wl.systems), "atoms": n_atoms,
-            "probes": wl.n_probes, "lanczos_steps": wl.n_steps, "block": wl.block,
-            "graph": graph,
-            "energy_forces_ms": round(1000 * t_ef, 2), "energy_only_ms": round(1000 * t_e, 2),
-            "forces_finite": ok,
-            "stage_ms": {k: round(v[0], 2) for k, v in stages.items() if v[1] > 0}}
+    log(f"{name}: E+F {t_ef:.1f} ms, E only {t_e:.1f} ms (median of {reps}, "
+        f"{'graph' if graph else 'eager'})")
+    return out
+
+
+def cpu_info():
+    model, cores = None, os.cpu_count()
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return model, cores
 
 
 def probe_vector(P, seed, system, probe, n):
@@ -267,14 +346,16 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--plain-probes", type=int, default=2)
+    ap.add_argument("--reps", type=int, default=10,
+                    help="graph replays per energy + forces median")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 B=1 leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 1 GiB device copy first (reference for HBM byte counters)")
     ap.add_argument("--no-forces", action="store_true",
-                    help="skip the energy + forces leg (12k-atom organic box)")
-    ap.add_argument("--uneven", action="store_true",
-                    help="also time the uneven batch (32 water boxes, energy + forces)")
+                    help="skip every energy + forces leg")
+    ap.add_argument("--no-uneven", action="store_true",
+                    help="skip the uneven batch (32 water boxes, energy + forces)")
     ap.add_argument("--eager", action="store_true",
                     help="launch every kernel from the host instead of replaying HIP graphs")
     ap.add_argument("--no-scs", action="store_true",
@@ -300,15 +381,17 @@ def main():
     A = synth.ANGSTROM_BOHR
     K = tuple(wl.grid) * 3 if len(wl.grid) == 1 else tuple(wl.grid)
     R, m, B = wl.n_probes, wl.n_steps, wl.block
+    graph = not args.eager
     log(f"workload: water N={s.n} L={s.cell[0, 0] / A:.2f} A K={K} R={R} m={m} B={B}")
-    ds = P.DeviceSystem(s.pos, s.cell, s.alpha, s.omega, s.rvdw)
-    prm = P.Params(real_cutoff=wl.real_cutoff_angstrom * A, grid=K, n_probes=R, n_steps=m,
-                   block=B, precision=P.PREC_MIXED, seed=wl.probe_seed, graph=not args.eager)
-    plan = P.Plan([ds], prm)
+    t0 = time.perf_counter()
+    _, plan = plan_for(P, synth, wl, forces=False, graph=graph, tune=True)
+    t_plan = time.perf_counter() - t0
     info = plan.info(0)
+    shape = shape_of(P, plan)
     n_pairs = int(info.n_pairs)
     log(f"tau={info.tau:.6f}/bohr r_pair={info.r_pair / A:.3f} A cells={list(info.cells)} "
-        f"pairs={n_pairs} workspace={info.workspace_bytes / 2**30:.2f} GiB")
+        f"pairs={n_pairs} workspace={info.workspace_bytes / 2**30:.2f} GiB shape={shape} "
+        f"(plan {t_plan:.2f} s)")
     pos = torch.as_tensor(s.pos, dtype=torch.float64, device="cuda")
 
     if args.calibrate_copy:
@@ -322,13 +405,14 @@ def main():
 
     def step():
         plan.set_positions(pos)
-        return plan.execute()
+        return plan.execute(energy_sd=True)
 
     for w in range(args.warmup):
-        e = step()
+        e, sd = step()
         torch.cuda.synchronize()
         plan.check()
         log(f"warmup {w}: E = {float(e[0]):.10e} Ha")
+
     def timed(n):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -339,24 +423,53 @@ def main():
 
     # The timed steps: execute replayed from its captured HIP graph (the plan's
     # production mode), or launched eagerly with --eager.
-    dt, e = timed(args.steps)
+    dt, (e, sd) = timed(args.steps)
     plan.check()
-    energy = float(e[0])
+    energy, energy_sd = float(e[0]), float(sd[0])
     ms_per_step = 1000.0 * dt / args.steps
     value = R * m * args.steps / dt
     log(f"timed {args.steps} steps ({'eager' if args.eager else 'graph replay'}): "
-        f"{ms_per_step:.2f} ms/step, {value:.1f} matvecs/s, E = {energy:.10e}")
-    # The same steps once more, launched eagerly with HIP events around every stage
-    # (per-stage times and the dominant kernel's roofline; not part of the value).
-    plan.stage_times()
-    plan.set_timing(True)
-    te, ee = timed(args.steps)
-    plan.set_timing(False)
-    plan.check()
-    stages = plan.stage_times()
-    assert float(ee[0]) == energy
+        f"{ms_per_step:.2f} ms/step, {value:.1f} matvecs/s, E = {energy:.10e} "
+        f"+- {energy_sd:.3e} Ha")
+    errors = {"quadrature_rel_err_8_probes": quadrature_error(plan,
+                                                              golden("water24k_quadrature"))}
+    rows = golden("water24k_rows")
+    if rows is not None:
+        v = torch.from_numpy(synth.gaussian_block(int(rows["block_seed"]), B, s.n)).cuda()
+        got = plan.matvec(v).cpu().numpy()[[int(c) for c in rows["columns"]]]
+        got = got[:, [int(i) for i in rows["sample"]]]
+        want = rows["rows"]
+        num = np.abs(got - want).reshape(len(want), -1).max(1)
+        den = np.abs(want).reshape(len(want), -1).max(1)
+        errors["matvec_elementwise_err_sampled_rows"] = float((num / den).max())
+    errors["oracle_reference"] = "tests/golden/water24k_quadrature.npz, water24k_rows.npz"
+    log(f"errors vs oracle: {errors}")
+    plan.close()
+
+    # Per-stage times: the same steps launched eagerly with HIP events around every
+    # stage, on one stream (the tuned shape without the side stream), so that each
+    # kernel's time is its own; not part of the value.
+    sh1 = {k: shape[k] for k in ("pair_wg_per_cu", "pair_subsets", "grid_chunk")}
+    sh1["overlap"] = 0
+    _, splan = plan_for(P, synth, wl, forces=False, graph=False, tune=False, shape=sh1)
+    splan.set_positions(pos)
+    splan.execute()
+    torch.cuda.synchronize()
+    splan.stage_times()
+    splan.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        splan.set_positions(pos)
+        ee = splan.execute()
+    torch.cuda.synchronize()
+    te = time.perf_counter() - t0
+    splan.set_timing(False)
+    splan.check()
+    stages = splan.stage_times()
+    splan.close()
     eager_rate = R * m * args.steps / te
-    log(f"eager with stage events: {1000 * te / args.steps:.2f} ms/step, "
+    log(f"eager one-stream with stage events: {1000 * te / args.steps:.2f} ms/step, "
         f"{eager_rate:.1f} matvecs/s")
 
     # Per-stage averages and the dominant kernel's roofline.
@@ -368,49 +481,68 @@ def main():
     if dom == "pair":
         flops = 18.0 * n_pairs * B
         achieved = flops / (dom_ms_avg * 1e-3) / 1e12
-        roof = {"kernel": "pair", "bound": "alu", "achieved": round(achieved, 3),
-                "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP32_VALU_PEAK_TFLOPS, 4),
-                "traffic": measured_traffic(STAGE_KERNEL.get(dom, "")),
+        roof = {"kernel": STAGE_KERNEL["pair"], "bound": "alu", "achieved": round(achieved, 3),
+                "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic(STAGE_KERNEL["pair"]),
+                "peak_nonpacked_fp32": FP32_NONPACKED_TFLOPS,
+                "frac_of_nonpacked_fp32": round(achieved / FP32_NONPACKED_TFLOPS, 4),
                 "avg_launch_ms": round(dom_ms_avg, 4),
                 "algorithmic_per_launch": f"18 flop x {n_pairs} pairs x {B} rhs"}
     else:
-        by = stage_bytes(dom, K, s.n, B)
+        by = stage_bytes(dom, K, s.n, B // 2)
         achieved = by / (dom_ms_avg * 1e-3) / 1e9
-        roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(STAGE_KERNEL.get(dom, "")), "avg_launch_ms": round(dom_ms_avg, 4),
+        roof = {"kernel": STAGE_KERNEL.get(dom, dom), "bound": "hbm",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(STAGE_KERNEL.get(dom, "")),
+                "avg_launch_ms": round(dom_ms_avg, 4),
                 "algorithmic_per_launch": f"{by:.4g} B"}
     # Whole-matvec algorithmic bytes 24 K^3 + 48 N per probe-vector.
     bmv = 24.0 * K[0] * K[1] * K[2] + 48.0 * s.n
-    path_gbs = bmv * value / 1e9
-    scs_leg = None if args.no_scs else scs_timing(plan, torch, s, n_pairs)
-    plan.close()
 
-    # Plain form: one probe vector at a time in float64, same kernels, same GPU.
-    plain_rate = None
+    scs_leg = None
+    if not args.no_scs:
+        _, sp = plan_for(P, synth, wl, forces=False, graph=False, tune=False)
+        scs_leg = scs_timing(sp, torch, s, n_pairs)
+        sp.close()
+
+    # Plain form: one probe vector at a time in float64, same kernels, same GPU,
+    # launched eagerly and replayed from a graph.
+    plain = None
     if not args.no_plain:
+        plain = {}
         Rp = args.plain_probes
-        prm_p = P.Params(real_cutoff=wl.real_cutoff_angstrom * A, grid=K, n_probes=Rp,
-                         n_steps=m, block=1, precision=P.PREC_FP64, seed=wl.probe_seed)
-        plain = P.Plan([ds], prm_p)
-        plain.execute()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        plain.execute()
-        torch.cuda.synchronize()
-        tp = time.perf_counter() - t0
-        plain.check()
-        plain_rate = Rp * m / tp
-        plain.close()
-        log(f"plain fp64 B=1: {plain_rate:.1f} matvecs/s")
+        for g in (False, True):
+            ds = P.DeviceSystem(s.pos, s.cell, s.alpha, s.omega, s.rvdw)
+            pp = P.Plan([ds], P.Params(real_cutoff=wl.real_cutoff_angstrom * A, grid=K,
+                                       n_probes=Rp, n_steps=m, block=1,
+                                       precision=P.PREC_FP64, seed=wl.probe_seed, graph=g))
+            pp.execute()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pp.execute()
+            torch.cuda.synchronize()
+            tp = time.perf_counter() - t0
+            pp.check()
+            plain["graph" if g else "eager"] = Rp * m / tp
+            pp.close()
+        log(f"plain fp64 B=1: {plain}")
+    plain_rate = max(plain.values()) if plain else None
 
-    graph = not args.eager
-    forces_leg = (None if args.no_forces
-                  else energy_forces_leg(P, torch, synth, "forces12k", graph))
-    # The uneven batch runs eagerly: its 32 systems overlap on 4 streams, which a replayed
-    # graph of that size did not keep (E+F 2.4 s replayed vs 2.1 s eager on one MI355X).
-    uneven_leg = energy_forces_leg(P, torch, synth, "uneven", False) if args.uneven else None
+    # E_MBD + forces: the headline box (the metric's second half), the 12k organic box
+    # and the uneven batch.
+    ef24 = ef12 = ef_uneven = None
+    if not args.no_forces:
+        ef24 = energy_forces_leg(P, torch, synth, "batched24k", graph, args.reps,
+                                 golden_name="water24k_quadrature")
+        ef12 = energy_forces_leg(P, torch, synth, "forces12k", graph, args.reps,
+                                 fp64_check=True, golden_name="organic12k_quadrature")
+        if not args.no_uneven:
+            ef_uneven = {"eager": energy_forces_leg(P, torch, synth, "uneven", False, 3,
+                                                    golden_name="uneven_quadrature")}
+            if graph:
+                ef_uneven["graph"] = energy_forces_leg(P, torch, synth, "uneven", True, 3)
 
     d11 = delta11_study(P, torch, synth) if args.delta11 else None
     bstudy = block_study(P, torch, synth) if args.block_study else None
@@ -418,23 +550,32 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import method as om
-        threads = torch.get_num_threads()
+        model, ncpu = cpu_info()
         op = om.Operator(s, om.MethodParams(tau=info.tau, r_pair=info.r_pair, grid=K,
                                             order=info.spline_order))
         y = torch.randn(s.n, 3, 1, dtype=torch.float64, generator=torch.Generator().manual_seed(0))
-        nmv = 12
-        t0 = time.perf_counter()
-        for _ in range(nmv):
-            op(y)
-        tc = time.perf_counter() - t0
-        cpu = {"value": round(nmv / tc, 4), "unit": "matvecs/s", "cores": threads,
-               "kind": "oracle",
-               "sample": f"{nmv} single-vector float64 SPME matvecs (same N, K, p, tau, r_pair) "
-                         f"with the CPU oracle, {tc:.1f} s"}
-        log(f"cpu oracle: {nmv / tc:.3f} matvecs/s on {threads} threads")
+        threads = torch.get_num_threads()
+
+        def rate(nmv):
+            t0 = time.perf_counter()
+            for _ in range(nmv):
+                op(y)
+            return nmv / (time.perf_counter() - t0), time.perf_counter() - t0
+
+        r_all, t_all = rate(12)
+        torch.set_num_threads(1)
+        r_one, t_one = rate(2)
+        torch.set_num_threads(threads)
+        cpu = {"value": round(r_all, 4), "unit": "matvecs/s", "cores": threads, "kind": "oracle",
+               "sample": f"12 single-vector float64 SPME matvecs of the 24k box (same N, K, p, "
+                         f"tau, r_pair) with the CPU oracle on {threads} threads, {t_all:.1f} s",
+               "cpu_model": model, "host_logical_cpus": ncpu,
+               "single_thread_value": round(r_one, 4),
+               "single_thread_sample": f"2 matvecs on 1 thread, {t_one:.1f} s"}
+        log(f"cpu oracle: {r_all:.3f} matvecs/s on {threads} threads, {r_one:.3f} on 1 ({model})")
 
     out = {
-        "metric": "probe-vector SPME matvecs/s at N=24k (batched, mixed precision)",
+        "metric": "probe-vector SPME matvecs/s and E_MBD+forces ms at N=24k, batched vs plain",
         "value": round(value, 1),
         "unit": "matvecs/s",
         "n_gpus": 1,
@@ -447,25 +588,30 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "water box N=24000, L=62.09 A, K=96^3, p=6, r_c=9 A, "
-                               "128 probes x 50 Lanczos steps as one RHS block",
+                               "128 probes x 50 Lanczos steps as one RHS block, mixed precision",
                    "n_atoms": s.n, "grid": list(K), "probes": R, "lanczos_steps": m,
-                   "block": B, "pairs": n_pairs},
+                   "block": B, "pairs": n_pairs, "shape": shape},
         "execution": "eager" if args.eager else "hip_graph_replay",
-        "eager_stage_timed_matvecs_per_s": round(eager_rate, 1),
         "energy_ms": round(ms_per_step, 3),
         "energy_ha": energy,
-        "plain_matvecs_per_s": round(plain_rate, 2) if plain_rate else None,
+        "energy_sd_ha": energy_sd,
+        "energy_forces_ms_24k": ef24["energy_forces_ms"] if ef24 else None,
+        "errors_vs_oracle": errors,
+        "plain_matvecs_per_s": {k: round(v, 2) for k, v in plain.items()} if plain else None,
         "speedup_vs_plain": round(value / plain_rate, 2) if plain_rate else None,
-        "path_algorithmic_GBps": round(path_gbs, 1),
-        "path_roofline_frac": round(path_gbs / HBM_PEAK_GBS, 4),
+        "path_algorithmic_GBps": round(bmv * value / 1e9, 1),
+        "path_roofline_frac": round(bmv * value / 1e9 / HBM_PEAK_GBS, 4),
+        "eager_one_stream_matvecs_per_s": round(eager_rate, 1),
         "stage_ms_per_step": {k: round(v, 3) for k, v in stage_ms.items()},
+        "stage_timing": "eager, one stream (tuned shape without the side stream), HIP events "
+                        "around every stage",
         "roofline": roof,
         "cpu_baseline": cpu,
-        "energy_forces": forces_leg,
+        "energy_forces_24k": ef24,
+        "energy_forces": ef12,
+        "energy_forces_uneven": ef_uneven,
         "scs": scs_leg,
     }
-    if uneven_leg is not None:
-        out["energy_forces_uneven"] = uneven_leg
     if d11 is not None:
         out["delta11"] = d11
     if bstudy is not None:

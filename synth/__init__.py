@@ -8,5 +8,5 @@ from .systems import (  # noqa: F401
     BOHR_ANGSTROM, ANGSTROM_BOHR, System, Workload,
     tiny_random, water_box, organic_mix, uneven_water_batch,
     one_atom, simple_cubic, dimer, diamond_box, workload,
-    SKEWED_CELL_ANGSTROM, triclinic_random,
+    SKEWED_CELL_ANGSTROM, triclinic_random, gaussian_block, sample_atoms,
 )

@@ -321,6 +321,17 @@ def diamond_box(n_cells: int = 4, a_ang: float = 3.567) -> System:
                   np.full(n, 0.45), np.full(n, 3.59))
 
 
+def gaussian_block(seed: int, nrhs: int, n_atoms: int) -> np.ndarray:
+    """Seeded standard-normal test vectors [nrhs][n_atoms][3] (numpy PCG64)."""
+    return np.random.default_rng(seed).standard_normal((nrhs, n_atoms, 3))
+
+
+def sample_atoms(seed: int, n_atoms: int, count: int = 64) -> np.ndarray:
+    """A seeded sorted sample of distinct atom indices."""
+    return np.sort(np.random.default_rng(seed).choice(n_atoms, min(count, n_atoms),
+                                                      replace=False))
+
+
 # A skewed right-handed cell (rows a1, a2, a3 in Angstrom) for the general-cell cases.
 SKEWED_CELL_ANGSTROM = np.array([[10.0, 0.0, 0.0], [2.6, 9.4, 0.0], [-1.7, 2.1, 10.8]])
 

@@ -14,6 +14,8 @@ Outputs (numpy .npz, no pickles), one per workload:
   organic12k_quadrature.npz 12,000-atom organic box, K = 80, 40 steps: probes 0 and 63
   uneven_quadrature.npz     batch of 32 water boxes, 40 steps: probe 0 of the smallest,
                             the median and the largest system
+  water24k_rows.npz         C v of the 24k box for four seeded Gaussian right-hand sides
+                            at 64 sampled atoms
 Each file also stores the parameters it was computed with (tau, r_pair, grid, order,
 seed, steps, probe indices, system index), which the tests check against the plan.
 
@@ -89,8 +91,29 @@ def uneven():
     return out
 
 
+def water24k_rows():
+    """C v for four right-hand sides (columns 0, 63, 64, 127 of the seeded Gaussian block
+    synth.gaussian_block(2024, 128, N)) at 64 sampled atoms (synth.sample_atoms(5, N)),
+    through the oracle's method operator with the derived parameters."""
+    wl = synth.workload("batched24k")
+    s = wl.systems[0]
+    tau, r_pair, K = derived(s, wl.real_cutoff_angstrom, [96] * 3)
+    op = om.Operator(s, om.MethodParams(tau=tau, r_pair=r_pair, grid=tuple(K), order=ORDER,
+                                        beta=BETA, d=DAMP))
+    cols = [0, 63, 64, 127]
+    v = synth.gaussian_block(2024, 128, s.n)[cols]
+    sample = synth.sample_atoms(5, s.n)
+    t0 = time.time()
+    import torch
+    out = op(torch.from_numpy(v).permute(1, 2, 0).contiguous()).permute(2, 0, 1)
+    print(f"  rows: {time.time() - t0:.0f} s", flush=True)
+    return dict(rows=out[:, sample].numpy(), columns=np.array(cols), sample=sample,
+                block_seed=2024, block=128, tau=tau, r_pair=r_pair, grid=np.array(K),
+                order=ORDER)
+
+
 MAKERS = {"water24k_quadrature": water24k, "organic12k_quadrature": organic12k,
-          "uneven_quadrature": uneven}
+          "uneven_quadrature": uneven, "water24k_rows": water24k_rows}
 
 
 def main(names):
