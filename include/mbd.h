@@ -81,8 +81,9 @@ typedef struct {
 
 /* Launch shape of one system's matvec. It changes how the work is laid out on the GPU:
  * pair_wg_per_cu, pair_subsets and overlap leave every result bit unchanged; grid_chunk
- * changes the summation order inside the spread and the gather, so results agree to
- * rounding across chunk widths. A plan is bitwise reproducible for its shape. */
+ * changes the summation order inside the spread and the gather, and gather_waves the
+ * grouping of the partial sums of a_k, so results agree to rounding across those. A plan
+ * is bitwise reproducible for its shape. */
 typedef struct {
   int32_t pair_wg_per_cu; /* work-groups per compute unit of the direct-space list kernel;
                              0 => one work-group per 16-atom target group (all resident)  */
@@ -94,6 +95,8 @@ typedef struct {
                              (single-system plans): 1 => forked before the spreads, 2 =>
                              forked after them (beside the transforms only); 0 => one
                              stream                                                       */
+  int32_t gather_waves;   /* wavefronts per work-group of the gather and the reciprocal
+                             force kernel: 4 or 8; 0 => 4                                 */
 } mbd_shape;
 
 enum {

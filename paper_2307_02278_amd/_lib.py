@@ -35,6 +35,7 @@ class MbdShape(C.Structure):
         ("pair_subsets", C.c_int32),
         ("grid_chunk", C.c_int32),
         ("overlap", C.c_int32),
+        ("gather_waves", C.c_int32),
     ]
 
 

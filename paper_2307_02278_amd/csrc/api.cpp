@@ -507,7 +507,7 @@ double* scratch_of(int device) {
 // bit unchanged; the grid chunk width changes the summation order of the spread and the
 // gather (sub-lanes share a stencil below 64 right-hand sides per chunk).
 
-constexpr mbd_shape kBuiltinShape = {0, 0, 0, 1};
+constexpr mbd_shape kBuiltinShape = {0, 0, 0, 1, 0};
 
 bool valid_shape(const mbd_shape& sh, int B) {
   const bool pow2chunk = sh.grid_chunk == 0 || (sh.grid_chunk > 0 && sh.grid_chunk <= 64 &&
@@ -515,13 +515,15 @@ bool valid_shape(const mbd_shape& sh, int B) {
   return sh.pair_wg_per_cu >= 0 && sh.pair_wg_per_cu <= 64 &&
          (sh.pair_subsets == 0 || sh.pair_subsets == 1 || sh.pair_subsets == 2 ||
           sh.pair_subsets == 4) &&
-         pow2chunk && sh.overlap >= 0 && sh.overlap <= 2;
+         pow2chunk && sh.overlap >= 0 && sh.overlap <= 2 &&
+         (sh.gather_waves == 0 || sh.gather_waves == 4 || sh.gather_waves == 8);
 }
 
 void apply_shape(const Plan& plan, System& S, const mbd_shape& sh) {
   S.shape = sh;
   S.geo.pair_blocks = sh.pair_wg_per_cu * plan.cus;
   S.geo.pair_ns = sh.pair_subsets;
+  S.geo.gather_waves = sh.gather_waves;
   S.BG = sh.grid_chunk > 0 ? sh.grid_chunk : plan.BG;
   // the per-system streams of a batch plan have no side stream
   S.overlap = plan.batch ? 0 : sh.overlap;
@@ -558,11 +560,12 @@ bool cache_lookup(const char* path, const std::string& key, mbd_shape& sh, doubl
   while (std::fgets(line, sizeof line, f)) {
     const std::string l(line);
     if (l.find(tag) == std::string::npos) continue;
-    double a, b, c, d, t = 0.0;
+    double a, b, c, d, e, t = 0.0;
     if (json_number(l, "pair_wg_per_cu", a) && json_number(l, "pair_subsets", b) &&
-        json_number(l, "grid_chunk", c) && json_number(l, "overlap", d)) {
+        json_number(l, "grid_chunk", c) && json_number(l, "overlap", d) &&
+        json_number(l, "gather_waves", e)) {
       json_number(l, "matvec_ms", t);
-      sh = mbd_shape{(int32_t)a, (int32_t)b, (int32_t)c, (int32_t)d};
+      sh = mbd_shape{(int32_t)a, (int32_t)b, (int32_t)c, (int32_t)d, (int32_t)e};
       ms = t;
       found = true;
     }
@@ -577,8 +580,10 @@ void cache_store(const char* path, const std::string& key, const mbd_shape& sh, 
   if (!f) return;
   std::fprintf(f,
                "{\"key\": \"%s\", \"pair_wg_per_cu\": %d, \"pair_subsets\": %d, "
-               "\"grid_chunk\": %d, \"overlap\": %d, \"matvec_ms\": %.5f}\n",
-               key.c_str(), sh.pair_wg_per_cu, sh.pair_subsets, sh.grid_chunk, sh.overlap, ms);
+               "\"grid_chunk\": %d, \"overlap\": %d, \"gather_waves\": %d, "
+               "\"matvec_ms\": %.5f}\n",
+               key.c_str(), sh.pair_wg_per_cu, sh.pair_subsets, sh.grid_chunk, sh.overlap,
+               sh.gather_waves, ms);
   std::fclose(f);
 }
 
@@ -612,8 +617,9 @@ double time_matvec(Plan& plan, System& S, int reps) {
 }
 
 // Coordinate search over the shape knobs on the system's real data: the pair kernel's
-// residency together with the side stream, then its lanes per target, then the grid
-// chunk width, then the residency once more under the chosen chunk.
+// residency together with the side stream, then its lanes per target, then the gather's
+// work-group size, then the grid chunk width, then the residency once more under the
+// chosen chunk.
 template <typename R>
 void tune_system(Plan& plan, System& S, int sys_index) {
   const int B = plan.B;
@@ -650,6 +656,11 @@ void tune_system(Plan& plan, System& S, int sys_index) {
       sh.pair_subsets = ns;
       trial(sh);
     }
+  }
+  {
+    mbd_shape sh = best;
+    sh.gather_waves = 8;
+    trial(sh);
   }
   {
     const mbd_shape base = best;
@@ -801,7 +812,8 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
     return fail(MBD_E_ARG, "tune must be MBD_TUNE_OFF, MBD_TUNE_MEASURE or MBD_TUNE_GIVEN");
   if (prm.tune == MBD_TUNE_GIVEN && !valid_shape(prm.shape, prm.block))
     return fail(MBD_E_ARG, "shape: pair_wg_per_cu in [0, 64], pair_subsets 0/1/2/4, grid_chunk "
-                           "0 or a power of two <= 64 dividing block, overlap 0/1/2");
+                           "0 or a power of two <= 64 dividing block, overlap 0/1/2, "
+                           "gather_waves 0/4/8");
 
   const int BG_plan = std::min(prm.block, prm.precision == MBD_PREC_FP64 ? 16 : 64);
   std::vector<Geometry> geos(n_sys);
@@ -1107,42 +1119,79 @@ mbd_status mbd_get_stage_times(mbd_plan plan, double* ms, int64_t* launches) {
 namespace mbd {
 namespace {
 
+// Enqueue the whole evaluation of system s on P.stream: its energy (and sd) into
+// energy[s] (sd[s]) and its forces, if requested, into forces at its atom offset.
+void enqueue_system(Plan& P, int s, double* energy, double* sd, double* forces) {
+  System& S = P.sys[s];
+  size_t off = 0;
+  for (int k = 0; k < s; ++k) off += (size_t)P.sys[k].geo.n;
+  if (forces) fill_double(S.buf.fsum, 0.0, 6 * (size_t)S.geo.n, P.stream);
+  double* sds = sd ? sd + s : nullptr;
+  if (P.prec == MBD_PREC_FP64) run_energy<double>(P, S, s, energy + s, sds, forces != nullptr);
+  else run_energy<float>(P, S, s, energy + s, sds, forces != nullptr);
+  if (forces)
+    staged(P, MBD_STAGE_ADJOINT, [&] {
+      launch_forces_finish(S.geo, S.buf, P.prm.n_probes, forces + 3 * off, P.stream);
+    });
+}
+
+// Enqueue, on P.stream, every system assigned to per-system stream j (all when j < 0).
+void enqueue_systems(Plan& P, int j, double* energy, double* sd, double* forces) {
+  for (int s = 0; s < (int)P.sys.size(); ++s)
+    if (j < 0 || P.sys_stream[s] == j) enqueue_system(P, s, energy, sd, forces);
+}
+
 // Enqueue one full evaluation (all systems) on plan.stream: clear the status word,
-// fork to the internal streams, run every system, join back.
+// fork to the per-system streams, run every system, join back.
 void enqueue_execute(Plan& P, double* energy, double* sd, double* forces) {
   const hipStream_t caller = P.stream;
   fill_int(reinterpret_cast<int*>(P.status), 0, 1, caller);
-  const bool fork = !P.pool.empty();
-  if (fork) {
-    check(hipEventRecord(P.fork, caller), "fork");
-    for (hipStream_t q : P.pool) check(hipStreamWaitEvent(q, P.fork, 0), "fork");
+  if (P.pool.empty()) {
+    enqueue_systems(P, -1, energy, sd, forces);
+    return;
   }
-  size_t off = 0;
+  check(hipEventRecord(P.fork, caller), "fork");
+  for (hipStream_t q : P.pool) check(hipStreamWaitEvent(q, P.fork, 0), "fork");
   try {
-    for (int s = 0; s < (int)P.sys.size(); ++s) {
-      System& S = P.sys[s];
-      if (fork) P.stream = P.pool[P.sys_stream[s]];  // this system's work goes to its stream
-      if (forces) fill_double(S.buf.fsum, 0.0, 6 * (size_t)S.geo.n, P.stream);
-      double* sds = sd ? sd + s : nullptr;
-      if (P.prec == MBD_PREC_FP64)
-        run_energy<double>(P, S, s, energy + s, sds, forces != nullptr);
-      else run_energy<float>(P, S, s, energy + s, sds, forces != nullptr);
-      if (forces)
-        staged(P, MBD_STAGE_ADJOINT, [&] {
-          launch_forces_finish(S.geo, S.buf, P.prm.n_probes, forces + 3 * off, P.stream);
-        });
-      off += (size_t)S.geo.n;
+    for (size_t j = 0; j < P.pool.size(); ++j) {
+      P.stream = P.pool[j];  // this stream's systems, one after another
+      enqueue_systems(P, (int)j, energy, sd, forces);
     }
   } catch (...) {
     P.stream = caller;
     throw;
   }
   P.stream = caller;
-  if (fork)
-    for (size_t i = 0; i < P.pool.size(); ++i) {
-      check(hipEventRecord(P.pool_done[i], P.pool[i]), "join");
-      check(hipStreamWaitEvent(caller, P.pool_done[i], 0), "join");
-    }
+  for (size_t i = 0; i < P.pool.size(); ++i) {
+    check(hipEventRecord(P.pool_done[i], P.pool[i]), "join");
+    check(hipStreamWaitEvent(caller, P.pool_done[i], 0), "join");
+  }
+}
+
+// Record the work of one stream into a graph: the whole evaluation on the capture stream
+// (single-system plans, with the side stream as a parallel branch), or the systems of
+// per-system stream j on that stream (batch plans).
+hipGraphExec_t record_graph(Plan& P, hipStream_t on, int j, double* forces) {
+  const hipStream_t caller = P.stream;
+  hipGraph_t g = nullptr;
+  P.stream = on;
+  check(hipStreamBeginCapture(on, hipStreamCaptureModeRelaxed), "begin capture");
+  try {
+    if (j < 0) enqueue_execute(P, P.e_out, P.sd_out, forces);
+    else enqueue_systems(P, j, P.e_out, P.sd_out, forces);
+  } catch (...) {
+    P.stream = caller;
+    hipStreamEndCapture(on, &g);
+    if (g) hipGraphDestroy(g);
+    throw;
+  }
+  P.stream = caller;
+  check(hipStreamEndCapture(on, &g), "end capture");
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  check(e, "graph instantiate");
+  return ex;
 }
 
 }  // namespace
@@ -1160,30 +1209,32 @@ mbd_status mbd_execute(mbd_plan plan, double* energy, double* forces, double* en
     } else {
       const int gi = forces ? 1 : 0;
       const hipStream_t caller = P.stream;
-      if (!P.gexec[gi]) {
-        hipGraph_t g = nullptr;
-        P.stream = P.gstream;  // the sequence is recorded from the plan's own stream
-        check(hipStreamBeginCapture(P.gstream, hipStreamCaptureModeRelaxed), "begin capture");
-        try {
-          enqueue_execute(P, P.e_out, P.sd_out, forces ? P.f_out : nullptr);
-        } catch (...) {
-          P.stream = caller;
-          hipStreamEndCapture(P.gstream, &g);
-          if (g) hipGraphDestroy(g);
-          throw;
+      double* fo = forces ? P.f_out : nullptr;
+      if (P.pool.empty()) {
+        // single system: one graph recorded from the plan's own stream (the caller's
+        // may be the null stream, which cannot be captured)
+        if (!P.gexec[gi]) P.gexec[gi] = record_graph(P, P.gstream, -1, fo);
+        // replay after the caller's earlier work; the caller's later work waits for it
+        check(hipEventRecord(P.g_in, caller), "graph fork");
+        check(hipStreamWaitEvent(P.gstream, P.g_in, 0), "graph fork");
+        check(hipGraphLaunch(P.gexec[gi], P.gstream), "graph launch");
+        check(hipEventRecord(P.g_out, P.gstream), "graph join");
+        check(hipStreamWaitEvent(caller, P.g_out, 0), "graph join");
+      } else {
+        // batch: one graph per per-system stream, replayed on that stream, so that the
+        // streams still run side by side
+        if (P.gpool[gi].empty())
+          for (size_t j = 0; j < P.pool.size(); ++j)
+            P.gpool[gi].push_back(record_graph(P, P.pool[j], (int)j, fo));
+        fill_int(reinterpret_cast<int*>(P.status), 0, 1, caller);
+        check(hipEventRecord(P.fork, caller), "graph fork");
+        for (size_t j = 0; j < P.pool.size(); ++j) {
+          check(hipStreamWaitEvent(P.pool[j], P.fork, 0), "graph fork");
+          check(hipGraphLaunch(P.gpool[gi][j], P.pool[j]), "graph launch");
+          check(hipEventRecord(P.pool_done[j], P.pool[j]), "graph join");
+          check(hipStreamWaitEvent(caller, P.pool_done[j], 0), "graph join");
         }
-        P.stream = caller;
-        check(hipStreamEndCapture(P.gstream, &g), "end capture");
-        const hipError_t e = hipGraphInstantiate(&P.gexec[gi], g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
-        check(e, "graph instantiate");
       }
-      // replay after the caller's earlier work; the caller's later work waits for it
-      check(hipEventRecord(P.g_in, caller), "graph fork");
-      check(hipStreamWaitEvent(P.gstream, P.g_in, 0), "graph fork");
-      check(hipGraphLaunch(P.gexec[gi], P.gstream), "graph launch");
-      check(hipEventRecord(P.g_out, P.gstream), "graph join");
-      check(hipStreamWaitEvent(caller, P.g_out, 0), "graph join");
       size_t nat = 0;
       for (const auto& S : P.sys) nat += (size_t)S.geo.n;
       check(hipMemcpyAsync(energy, P.e_out, sizeof(double) * P.sys.size(),
@@ -1464,6 +1515,9 @@ mbd_status mbd_plan_destroy(mbd_plan plan) {
   }
   for (hipGraphExec_t g : plan->plan.gexec)
     if (g) hipGraphExecDestroy(g);
+  for (const auto& v : plan->plan.gpool)
+    for (hipGraphExec_t g : v)
+      if (g) hipGraphExecDestroy(g);
   if (plan->plan.g_in) hipEventDestroy(plan->plan.g_in);
   if (plan->plan.g_out) hipEventDestroy(plan->plan.g_out);
   if (plan->plan.gstream) hipStreamDestroy(plan->plan.gstream);

@@ -50,6 +50,7 @@ struct Geometry {
   // launch shape of the direct-space list kernels (set by the plan or its tuner)
   int pair_blocks;       // work-groups of a launch; 0 => one per 16-atom group
   int pair_ns;           // target subsets per wavefront (1, 2, 4); 0 => size rule
+  int gather_waves;      // wavefronts per work-group of the gather-type kernels (4 or 8)
 };
 
 // Cells are numbered along a Morton (Z-order) curve so that consecutive sorted
@@ -218,6 +219,7 @@ struct Plan {
   hipStream_t gstream = nullptr;  // capture and replay stream (the caller's may be the null stream)
   hipEvent_t g_in = nullptr, g_out = nullptr;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  std::vector<hipGraphExec_t> gpool[2];  // batch plans: one graph per per-system stream
   double* e_out = nullptr;       // [n_sys]
   double* f_out = nullptr;       // [sum n][3] (forces plans)
   double* sd_out = nullptr;      // [n_sys] standard deviation of the energy estimate

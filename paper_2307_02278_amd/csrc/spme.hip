@@ -170,7 +170,7 @@ k_spread(const Geometry geo, const int* __restrict__ tile_start,
 }
 
 template <typename R, int P, int BG>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 k_gather_epilogue(const Geometry geo, const int* __restrict__ base, const R* __restrict__ th,
                   const R* __restrict__ dth, const R* __restrict__ grid, size_t chunk_elems,
                   const R* __restrict__ Ed, const double* __restrict__ w,
@@ -178,7 +178,8 @@ k_gather_epilogue(const Geometry geo, const int* __restrict__ base, const R* __r
                   uint32_t comps, double self_coef, double* __restrict__ lt,
                   double* __restrict__ part, int chunk0) {
   constexpr int NSUB = Lanes<BG>::NSUB;
-  __shared__ double red[256];
+  __shared__ double red[512];
+  const int nw = blockDim.x >> 6;  // wavefronts per work-group (4 or 8)
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int lane = threadIdx.x & 63;
   const int b = lane % BG;
@@ -195,8 +196,8 @@ k_gather_epilogue(const Geometry geo, const int* __restrict__ base, const R* __r
   // any time are consecutive, i.e. spatially compact, and their stencils share L2.
   const int nb8 = gridDim.x / 8;
   const int xcd = blockIdx.x % 8;
-  const int nwx = nb8 * 4;
-  const int lw = (blockIdx.x / 8) * 4 + wave;
+  const int nwx = nb8 * nw;
+  const int lw = (blockIdx.x / 8) * nw + wave;
   const int x_lo = (int)(((long)geo.n * xcd) / 8);
   const int x_hi = (int)(((long)geo.n * (xcd + 1)) / 8);
   for (int s = x_lo + lw; s < x_hi; s += nwx) {
@@ -271,12 +272,12 @@ k_gather_epilogue(const Geometry geo, const int* __restrict__ base, const R* __r
       }
     }
   }
-  // per-RHS sum over the four wavefronts (sub-lanes hold zero)
+  // per-RHS sum over the work-group's wavefronts (sub-lanes hold zero)
   red[threadIdx.x] = dot;
   __syncthreads();
   if (threadIdx.x < BG) {
     double t = 0.0;
-    for (int wv = 0; wv < 4; ++wv)
+    for (int wv = 0; wv < nw; ++wv)
       for (int sb = 0; sb < NSUB; ++sb) t += red[wv * 64 + sb * BG + threadIdx.x];
     part[((size_t)blockIdx.x * kPartSlots + 0) * B + chunk * BG + threadIdx.x] = t;
   }
@@ -290,12 +291,13 @@ k_gather_epilogue(const Geometry geo, const int* __restrict__ base, const R* __r
 // other dipole set h, summed over the chunk's right-hand sides, to fsum (wavefront
 // per atom, lanes over right-hand sides and stencil rows as in the gather).
 template <typename R, int P, int BG>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 k_spme_force(const Geometry geo, const int* __restrict__ base, const R* __restrict__ th,
              const R* __restrict__ dth, const R* __restrict__ ddth, const R* __restrict__ grid,
              size_t chunk_elems, const R* __restrict__ hv, int B, int chunk0,
              double* __restrict__ fsum) {
   constexpr int NSUB = Lanes<BG>::NSUB;
+  const int nw = blockDim.x >> 6;  // wavefronts per work-group (4 or 8)
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int lane = threadIdx.x & 63;
   const int b = lane % BG;
@@ -307,8 +309,8 @@ k_spme_force(const Geometry geo, const int* __restrict__ base, const R* __restri
   const int XS = K1 + 2;
   const int nb8 = gridDim.x / 8;
   const int xcd = blockIdx.x % 8;
-  const int nwx = nb8 * 4;
-  const int lw = (blockIdx.x / 8) * 4 + wave;
+  const int nwx = nb8 * nw;
+  const int lw = (blockIdx.x / 8) * nw + wave;
   const int x_lo = (int)(((long)geo.n * xcd) / 8);
   const int x_hi = (int)(((long)geo.n * (xcd + 1)) / 8);
   for (int s = x_lo + lw; s < x_hi; s += nwx) {
@@ -382,6 +384,10 @@ k_spme_force(const Geometry geo, const int* __restrict__ base, const R* __restri
   }
 }
 
+// Wavefronts per work-group of the gather-type kernels (one atom per wavefront at a
+// time; kRedBlocks work-groups per chunk).
+int gather_waves(const Geometry& geo) { return geo.gather_waves == 8 ? 8 : 4; }
+
 }  // namespace
 
 template <typename R>
@@ -420,7 +426,7 @@ void launch_epilogue(const Geometry& geo, const SysBuffers& b, const double* w, 
   dim3 grd(kRedBlocks, nchunks);
   const double self_coef = -4.0 * geo.tau * geo.tau * geo.tau / (3.0 * sqrt(M_PI));
 #define MBD_GATHER(PP, BB)                                                                  \
-  k_gather_epilogue<R, PP, BB><<<grd, 256, 0, st>>>(                                       \
+  k_gather_epilogue<R, PP, BB><<<grd, 64 * gather_waves(geo), 0, st>>>(                   \
       geo, b.base, (const R*)b.th, (const R*)b.dth, (const R*)b.grid, chunk,               \
       (const R*)b.Ed, w, b.g, b.om2, B, comps, self_coef, b.Lt, b.part, chunk0)
 #define MBD_GATHER_P(BB)                    \
@@ -448,7 +454,8 @@ void launch_spme_force(const Geometry& geo, const SysBuffers& b, const void* h, 
   const size_t chunk = (size_t)geo.K[2] * geo.K[1] * (geo.K[0] + 2) * BG;
   dim3 grd(kRedBlocks, 1);
 #define MBD_SF(PP, BB)                                                                      \
-  k_spme_force<R, PP, BB><<<grd, 256, 0, st>>>(geo, b.base, (const R*)b.th, (const R*)b.dth, \
+  k_spme_force<R, PP, BB><<<grd, 64 * gather_waves(geo), 0, st>>>(                       \
+      geo, b.base, (const R*)b.th, (const R*)b.dth,                                         \
                                                (const R*)b.ddth, (const R*)b.grid, chunk,     \
                                                (const R*)h, B, chunk0, b.fsum)
 #define MBD_SF_P(BB)                 \

@@ -2,7 +2,8 @@
 list-kernel residency, the lanes per target and the side stream for the pair kernel
 leave every result bit unchanged; the grid chunk width changes the order of the
 spread's and the gather's sums (sub-lanes share a stencil when fewer than 64 right-hand
-sides form a chunk), so results then agree to rounding. Every shape must match the
+sides form a chunk) and the gather's work-group size the grouping of the partial sums of
+a_k, so results then agree to rounding. Every shape must match the
 oracle; a measured shape is stored in the cache file and taken from there by the next
 plan with the same key."""
 import json
@@ -39,7 +40,9 @@ SHAPES = [dict(pair_wg_per_cu=0, pair_subsets=0, grid_chunk=0, overlap=1),
           dict(pair_wg_per_cu=2, pair_subsets=1, grid_chunk=0, overlap=0),
           dict(pair_wg_per_cu=3, pair_subsets=2, grid_chunk=64, overlap=2),
           dict(pair_wg_per_cu=0, pair_subsets=2, grid_chunk=32, overlap=2),
-          dict(pair_wg_per_cu=1, pair_subsets=4, grid_chunk=16, overlap=1)]
+          dict(pair_wg_per_cu=1, pair_subsets=4, grid_chunk=16, overlap=1),
+          dict(pair_wg_per_cu=0, pair_subsets=0, grid_chunk=0, overlap=1, gather_waves=8),
+          dict(pair_wg_per_cu=2, pair_subsets=2, grid_chunk=64, overlap=2, gather_waves=8)]
 
 
 def test_shapes_give_the_same_bits_and_match_the_oracle(water600):
@@ -56,9 +59,10 @@ def test_shapes_give_the_same_bits_and_match_the_oracle(water600):
         out = plan.matvec(v.cuda()).cpu()
         e, f = plan.execute(forces=True)
         plan.check()
-        res.append((out, e.cpu(), f.cpu(), inf.shape.grid_chunk or 64))
+        res.append((out, e.cpu(), f.cpu(), (inf.shape.grid_chunk or 64,
+                                             inf.shape.gather_waves or 4)))
         plan.close()
-    # the same chunk width: the same bits
+    # the same chunk width and gather work-group: the same bits
     for k in range(1, len(SHAPES)):
         same = [j for j in range(k) if res[j][3] == res[k][3]]
         for j in same[:1]:
@@ -100,7 +104,7 @@ def test_measured_shape_is_cached_and_reused(water600, tmp_path):
     second = _plan(s, P.TUNE_MEASURE, cache=cache)
     inf2 = second.info(0)
     assert inf2.shape_source == 2
-    for k in ("pair_wg_per_cu", "pair_subsets", "grid_chunk", "overlap"):
+    for k in ("pair_wg_per_cu", "pair_subsets", "grid_chunk", "overlap", "gather_waves"):
         assert getattr(inf2.shape, k) == getattr(inf.shape, k)
     e2 = second.execute()
     second.check()
