@@ -80,15 +80,19 @@ typedef struct {
 } mbd_system;
 
 /* Launch shape of one system's matvec. It changes how the work is laid out on the GPU:
- * pair_wg_per_cu, pair_subsets and overlap leave every result bit unchanged; grid_chunk
- * changes the summation order inside the spread and the gather, and gather_waves the
- * grouping of the partial sums of a_k, so results agree to rounding across those. A plan
- * is bitwise reproducible for its shape. */
+ * pair_wg_per_cu, pair_subsets (vector pair kernel) and overlap leave every result bit
+ * unchanged; grid_chunk changes the summation order inside the spread and the gather,
+ * gather_waves the grouping of the partial sums of a_k, and pair_mode (with pair_subsets
+ * under it) the order of the direct-space sums, so results agree to rounding across
+ * those. A plan is bitwise reproducible for its shape. */
 typedef struct {
   int32_t pair_wg_per_cu; /* work-groups per compute unit of the direct-space list kernel;
                              0 => one work-group per 16-atom target group (all resident)  */
-  int32_t pair_subsets;   /* target subsets per list-kernel wavefront: 1, 2 or 4 (at least
-                             64 / block); 0 => the size rule (4096 wavefronts or more)    */
+  int32_t pair_subsets;   /* vector list kernel: target subsets per wavefront, 1, 2 or 4
+                             (at least 64 / block); 0 => the size rule (4096 wavefronts
+                             or more). Matrix-core kernel: wavefronts that share one
+                             group's candidates, 1, 2 or 4 (at most 4 wavefronts per
+                             work-group with block / 64 column wavefronts); 0 => 1      */
   int32_t grid_chunk;     /* right-hand sides per SPME grid chunk: a power of two <= 64
                              that divides block; 0 => 64 (mixed) or 16 (float64)         */
   int32_t overlap;        /* pair kernel on a side stream, concurrent with the grid stages
@@ -97,6 +101,16 @@ typedef struct {
                              stream                                                       */
   int32_t gather_waves;   /* wavefronts per work-group of the gather and the reciprocal
                              force kernel: 4 or 8; 0 => 4                                 */
+  int32_t spread_mode;    /* 0 => spread over 4x4x4 grid tiles, then the forward x
+                             transform as its own pass; 1 => spread along whole x-lines
+                             fused with the forward x transform (mixed precision, p = 6,
+                             64-wide chunks; otherwise 0 is used). Both give the same
+                             real grid; the fused form never writes it                  */
+  int32_t pair_mode;      /* direct-space list kernel: 0 => vector FMA lanes, one lane per
+                             right-hand side, skipping out-of-range pairs; 1 => matrix
+                             cores (v_mfma_f32_16x16x4_f32) over the dense per-group
+                             product (mixed precision, block a multiple of 64 up to 256;
+                             otherwise 0 is used)                                        */
 } mbd_shape;
 
 enum {

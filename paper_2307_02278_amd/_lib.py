@@ -36,6 +36,8 @@ class MbdShape(C.Structure):
         ("grid_chunk", C.c_int32),
         ("overlap", C.c_int32),
         ("gather_waves", C.c_int32),
+        ("spread_mode", C.c_int32),
+        ("pair_mode", C.c_int32),
     ]
 
 

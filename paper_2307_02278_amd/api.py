@@ -31,7 +31,8 @@ class Params:
     replica_cutoff: float = 0.0     # bohr; > 0 => replica method (float64, energy only)
     krylov_block: int = 1           # > 1 => block Lanczos over blocks of this many probes
     tune: int = L.TUNE_OFF          # TUNE_OFF / TUNE_MEASURE / TUNE_GIVEN
-    shape: Optional[dict] = None    # TUNE_GIVEN: pair_wg_per_cu, pair_subsets, grid_chunk, overlap
+    shape: Optional[dict] = None    # TUNE_GIVEN: mbd_shape fields (pair_wg_per_cu, pair_subsets,
+    #                                 grid_chunk, overlap, gather_waves, spread_mode, pair_mode)
     tune_cache: Optional[str] = None  # TUNE_MEASURE: JSON-lines cache file
 
     def to_c(self) -> L.MbdParams:

@@ -168,6 +168,12 @@ void allocate_system(Plan& plan, System& S, int R_probes, int m) {
   size_t per_atom = 1;
   for (int a = 0; a < 3; ++a) per_atom *= (size_t)((g.p - 1 + g.tile[a] - 1) / g.tile[a] + 2);
   b.tile_atoms = dalloc<int>(plan, per_atom * (size_t)n, by);
+  if (sizeof(R) == 4 && g.p == 6 && n < (1 << 23)) {  // line entries pack s << 8
+    const size_t nlines = (size_t)g.K[1] * g.K[2];
+    b.line_count = dalloc<int>(plan, nlines + 1, by);
+    b.line_start = dalloc<int>(plan, nlines + 1, by);
+    b.line_atoms = dalloc<int>(plan, (size_t)g.p * g.p * n, by);
+  }
   b.G = dalloc<R>(plan, (size_t)g.K[2] * g.K[1] * (g.K[0] / 2 + 1), by);
   b.tw = dalloc<R>(plan, 2 * (size_t)(g.K[0] + g.K[1] + g.K[2]), by);
   const size_t vec = 3 * (size_t)n * B;
@@ -282,8 +288,25 @@ void create_pair_list(Plan& plan, System& S) {
   b.pg_cap = ((mx + mx / 4 + 32) + 15) / 16 * 16;
   b.pg_hdr = dalloc<int2>(plan, (size_t)ngroups * b.pg_cap, S.bytes);
   b.pg_T = dalloc<R>(plan, (size_t)ngroups * b.pg_cap * kCandStride, S.bytes);
+  b.pg_zero = dalloc<R>(plan, kTensorWords, S.bytes);
+  check(hipMemset(b.pg_zero, 0, kTensorWords * sizeof(R)), "zero tensor");
   if (plan.forces) b.pg_F = dalloc<R>(plan, (size_t)ngroups * b.pg_cap * kCandStride, S.bytes);
   launch_pair_build<R>(S.geo, b, false, plan.stream);
+}
+
+// Spread of grid chunk c of the dipoles in b.dv, fused with the forward x pass when the
+// system's shape selects the line spread; returns the first transform pass still to run
+// (1 after the fused spread, else 0).
+template <typename R>
+int spread_chunk(Plan& plan, System& S, const SysBuffers& b, int c, hipStream_t st) {
+  int first = 0;
+  staged(plan, MBD_STAGE_SPREAD, [&] {
+    if (S.shape.spread_mode == 1 && launch_spread_xline(S.geo, b, plan.B, S.BG, c, 1, st))
+      first = 1;
+    else
+      launch_spread<R>(S.geo, b, plan.B, S.BG, c, 1, st);
+  });
+  return first;
 }
 
 // The adjoint matvec C lbar_k (into Lt) together with the bilinear force terms
@@ -309,11 +332,11 @@ void adjoint_matvec_forces(Plan& plan, System& S) {
     staged_on(plan, MBD_STAGE_FORCE, ss, [&] { launch_pair_force<R>(S.geo, b, plan.B, ss); });
   };
   if (S.overlap != 2) pair_work();
-  for (int c = 0; c < nch; ++c)
-    staged(plan, MBD_STAGE_SPREAD, [&] { launch_spread<R>(S.geo, b, plan.B, BG, c, 1, st); });
+  int first = 0;
+  for (int c = 0; c < nch; ++c) first = spread_chunk<R>(plan, S, b, c, st);
   if (S.overlap == 2) pair_work();
   for (int c = 0; c < nch; ++c)
-    for (int pass = 0; pass < 5; ++pass)
+    for (int pass = first; pass < 5; ++pass)
       staged(plan, MBD_STAGE_FFT_X + pass,
              [&] { launch_fft_pass<R>(S.geo, b, plan.B, BG, c, 1, pass, st); });
   if (sd) check(hipStreamWaitEvent(st, sd->pair_done, 0), "side join");
@@ -323,9 +346,8 @@ void adjoint_matvec_forces(Plan& plan, System& S) {
     });
     staged(plan, MBD_STAGE_FORCE,
            [&] { launch_spme_force<R>(S.geo, b, b.dq, plan.B, BG, c, st); });
-    staged(plan, MBD_STAGE_SPREAD,
-           [&] { launch_spread<R>(S.geo, bq, plan.B, BG, c, 1, st); });
-    for (int pass = 0; pass < 5; ++pass)
+    const int fq = spread_chunk<R>(plan, S, bq, c, st);
+    for (int pass = fq; pass < 5; ++pass)
       staged(plan, MBD_STAGE_FFT_X + pass,
              [&] { launch_fft_pass<R>(S.geo, bq, plan.B, BG, c, 1, pass, st); });
     staged(plan, MBD_STAGE_FORCE,
@@ -378,14 +400,13 @@ void matvec_block(Plan& plan, System& S, const double* w, uint32_t comps) {
   };
   const bool rec = (comps & MBD_C_REC) != 0;
   if ((comps & MBD_C_DIR) && (S.overlap != 2 || !rec)) pair_work();
+  int first = 0;
   if (rec)
-    for (int c = 0; c < nch; ++c)
-      staged(plan, MBD_STAGE_SPREAD,
-             [&] { launch_spread<R>(S.geo, S.buf, plan.B, BG, c, 1, st); });
+    for (int c = 0; c < nch; ++c) first = spread_chunk<R>(plan, S, S.buf, c, st);
   if ((comps & MBD_C_DIR) && S.overlap == 2 && rec) pair_work();
   if (rec)
     for (int c = 0; c < nch; ++c)
-      for (int pass = 0; pass < 5; ++pass)
+      for (int pass = first; pass < 5; ++pass)
         staged(plan, MBD_STAGE_FFT_X + pass,
                [&] { launch_fft_pass<R>(S.geo, S.buf, plan.B, BG, c, 1, pass, st); });
   if (sd) join_side(st, sd->side, sd->pair_done);
@@ -505,9 +526,10 @@ double* scratch_of(int device) {
 // A shape only changes how a system's matvec is laid out on the GPU: work-groups of the
 // list kernel, lanes per target and a side stream for the pair kernel leave every result
 // bit unchanged; the grid chunk width changes the summation order of the spread and the
-// gather (sub-lanes share a stencil below 64 right-hand sides per chunk).
+// gather (sub-lanes share a stencil below 64 right-hand sides per chunk), and the
+// matrix-core pair kernel the order of the direct-space sums.
 
-constexpr mbd_shape kBuiltinShape = {0, 0, 0, 1, 0};
+constexpr mbd_shape kBuiltinShape = {0, 0, 0, 1, 0, 0, 0};
 
 bool valid_shape(const mbd_shape& sh, int B) {
   const bool pow2chunk = sh.grid_chunk == 0 || (sh.grid_chunk > 0 && sh.grid_chunk <= 64 &&
@@ -516,7 +538,9 @@ bool valid_shape(const mbd_shape& sh, int B) {
          (sh.pair_subsets == 0 || sh.pair_subsets == 1 || sh.pair_subsets == 2 ||
           sh.pair_subsets == 4) &&
          pow2chunk && sh.overlap >= 0 && sh.overlap <= 2 &&
-         (sh.gather_waves == 0 || sh.gather_waves == 4 || sh.gather_waves == 8);
+         (sh.gather_waves == 0 || sh.gather_waves == 4 || sh.gather_waves == 8) &&
+         (sh.spread_mode == 0 || sh.spread_mode == 1) &&
+         (sh.pair_mode == 0 || sh.pair_mode == 1);
 }
 
 void apply_shape(const Plan& plan, System& S, const mbd_shape& sh) {
@@ -528,6 +552,21 @@ void apply_shape(const Plan& plan, System& S, const mbd_shape& sh) {
   // the per-system streams of a batch plan have no side stream
   S.overlap = plan.batch ? 0 : sh.overlap;
   S.shape.overlap = S.overlap;
+  // the fused line spread exists for float grids, p = 6 and 64-wide chunks
+  if (!(plan.prec == MBD_PREC_MIXED && S.geo.p == 6 && S.BG == 64 && S.buf.line_start))
+    S.shape.spread_mode = 0;
+  // its atom lists are built from here on (and by every later setup) only when used
+  const int lines = S.shape.spread_mode == 1 ? 1 : 0;
+  if (lines && !S.geo.line_lists) {
+    S.geo.line_lists = 1;
+    launch_line_lists(S.geo, S.buf, plan.stream);
+  }
+  S.geo.line_lists = lines;
+  // the matrix-core list kernel exists for float tensors and block = 64, 128, 192, 256
+  if (!(plan.prec == MBD_PREC_MIXED && plan.B % 64 == 0 && plan.B <= 256 && S.buf.pg_T &&
+        S.geo.replica_cut <= 0.0))
+    S.shape.pair_mode = 0;
+  S.geo.pair_mode = S.shape.pair_mode;
 }
 
 std::string shape_key(const Plan& plan, const System& S) {
@@ -560,12 +599,14 @@ bool cache_lookup(const char* path, const std::string& key, mbd_shape& sh, doubl
   while (std::fgets(line, sizeof line, f)) {
     const std::string l(line);
     if (l.find(tag) == std::string::npos) continue;
-    double a, b, c, d, e, t = 0.0;
+    double a, b, c, d, e, f, g = 0.0, t = 0.0;
     if (json_number(l, "pair_wg_per_cu", a) && json_number(l, "pair_subsets", b) &&
         json_number(l, "grid_chunk", c) && json_number(l, "overlap", d) &&
-        json_number(l, "gather_waves", e)) {
+        json_number(l, "gather_waves", e) && json_number(l, "spread_mode", f)) {
+      json_number(l, "pair_mode", g);
       json_number(l, "matvec_ms", t);
-      sh = mbd_shape{(int32_t)a, (int32_t)b, (int32_t)c, (int32_t)d, (int32_t)e};
+      sh = mbd_shape{(int32_t)a, (int32_t)b, (int32_t)c, (int32_t)d, (int32_t)e, (int32_t)f,
+                     (int32_t)g};
       ms = t;
       found = true;
     }
@@ -581,9 +622,9 @@ void cache_store(const char* path, const std::string& key, const mbd_shape& sh, 
   std::fprintf(f,
                "{\"key\": \"%s\", \"pair_wg_per_cu\": %d, \"pair_subsets\": %d, "
                "\"grid_chunk\": %d, \"overlap\": %d, \"gather_waves\": %d, "
-               "\"matvec_ms\": %.5f}\n",
+               "\"spread_mode\": %d, \"pair_mode\": %d, \"matvec_ms\": %.5f}\n",
                key.c_str(), sh.pair_wg_per_cu, sh.pair_subsets, sh.grid_chunk, sh.overlap,
-               sh.gather_waves, ms);
+               sh.gather_waves, sh.spread_mode, sh.pair_mode, ms);
   std::fclose(f);
 }
 
@@ -617,9 +658,12 @@ double time_matvec(Plan& plan, System& S, int reps) {
 }
 
 // Coordinate search over the shape knobs on the system's real data: the pair kernel's
-// residency together with the side stream, then its lanes per target, then the gather's
-// work-group size, then the grid chunk width, then the residency once more under the
-// chosen chunk.
+// residency together with the side stream, then its lanes per target or the matrix-core
+// kernel with its candidate split, then the gather's work-group size, then the grid
+// chunk width, then the residency once more under the chosen chunk. The fused x-line
+// spread is left out: it runs about four times slower than the tile spread plus the x
+// pass on a 96^3 grid with 24,000 atoms (each atom's loads and weights are repeated on
+// all 36 lines it touches).
 template <typename R>
 void tune_system(Plan& plan, System& S, int sys_index) {
   const int B = plan.B;
@@ -656,6 +700,15 @@ void tune_system(Plan& plan, System& S, int sys_index) {
       sh.pair_subsets = ns;
       trial(sh);
     }
+    // the matrix-core kernel with 1, 2 or 4 wavefronts per group's candidates
+    if (plan.prec == MBD_PREC_MIXED && B % 64 == 0 && B <= 256)
+      for (int nk : {1, 2, 4}) {
+        if ((B / 64) * nk > 4) continue;
+        mbd_shape sh = base;
+        sh.pair_mode = 1;
+        sh.pair_subsets = nk;
+        trial(sh);
+      }
   }
   {
     mbd_shape sh = best;
@@ -813,7 +866,7 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
   if (prm.tune == MBD_TUNE_GIVEN && !valid_shape(prm.shape, prm.block))
     return fail(MBD_E_ARG, "shape: pair_wg_per_cu in [0, 64], pair_subsets 0/1/2/4, grid_chunk "
                            "0 or a power of two <= 64 dividing block, overlap 0/1/2, "
-                           "gather_waves 0/4/8");
+                           "gather_waves 0/4/8, spread_mode 0/1, pair_mode 0/1");
 
   const int BG_plan = std::min(prm.block, prm.precision == MBD_PREC_FP64 ? 16 : 64);
   std::vector<Geometry> geos(n_sys);

@@ -51,6 +51,8 @@ struct Geometry {
   int pair_blocks;       // work-groups of a launch; 0 => one per 16-atom group
   int pair_ns;           // target subsets per wavefront (1, 2, 4); 0 => size rule
   int gather_waves;      // wavefronts per work-group of the gather-type kernels (4 or 8)
+  int pair_mode;         // 0 => vector list kernel; 1 => matrix-core list kernel (float)
+  int line_lists;        // 1 => the setup also builds the x-line atom lists (fused spread)
 };
 
 // Cells are numbered along a Morton (Z-order) curve so that consecutive sorted
@@ -122,6 +124,11 @@ struct SysBuffers {
   int* tile_count = nullptr;   // [ntiles + 1]
   int* tile_start = nullptr;   // [ntiles + 1]
   int* tile_atoms = nullptr;   // [n * max tiles per stencil]
+  // x-line lists of the fused line spread (float plans): for each line y + K2 z, the atoms
+  // whose y-z stencil covers it, in atom order, as (s << 8) | (t_y << 4) | t_z
+  int* line_count = nullptr;   // [K2 K3 + 1]
+  int* line_start = nullptr;   // [K2 K3 + 1]
+  int* line_atoms = nullptr;   // [p^2 n]
   void* G = nullptr;           // Real [K3][K2][K1/2 + 1]
   void* tw = nullptr;          // Real [2][K1 + K2 + K3] twiddles exp(-2 pi i j / K_a)
   int* images = nullptr;       // [n_images][3] integer lattice vectors (replica method)
@@ -131,6 +138,7 @@ struct SysBuffers {
   int* pg_max = nullptr;       // [1] max over groups of pg_count
   int2* pg_hdr = nullptr;      // [ngroups][pg_cap] (source index, 16-bit target mask)
   void* pg_T = nullptr;        // Real [ngroups][pg_cap][kGroup][kTensorWords]
+  void* pg_zero = nullptr;     // Real [kTensorWords] zeros (matrix-core rows past a list)
   // Lanczos state for one block of right-hand sides
   double* W = nullptr;         // [m][n][3][B] Krylov vectors, unnormalized
   double* Lt = nullptr;        // [n][3][B] C w_k
@@ -232,6 +240,7 @@ struct Plan {
 // ---------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files). All enqueue on `st`.
 // ---------------------------------------------------------------------------
+void launch_line_lists(const Geometry& g, SysBuffers& b, hipStream_t st);
 template <typename R>
 void launch_setup(const Geometry& g, SysBuffers& b, const double* pos, const double* alpha,
                   const double* omega, const double* rvdw, hipStream_t st);
@@ -254,6 +263,10 @@ void launch_spread(const Geometry& g, const SysBuffers& b, int B, int BG, int ch
 template <typename R>
 void launch_fft_pass(const Geometry& g, const SysBuffers& b, int B, int BG, int chunk0,
                      int nchunks, int pass, hipStream_t st);
+// Spread fused with the forward x pass (float, 64-wide chunks, p = 6); false when this
+// case is not compiled (then k_spread and pass 0 run instead).
+bool launch_spread_xline(const Geometry& g, const SysBuffers& b, int B, int BG, int chunk0,
+                         int nchunks, hipStream_t st);
 
 void fill_int(int* p, int v, int n, hipStream_t st);
 

@@ -581,6 +581,136 @@ k_fft_x_real(float* __restrict__ grid, GridDims gd) {
   }
 }
 
+// Spread along whole x-lines fused with the forward real x transform (float, 64
+// right-hand sides per chunk, order P): one wavefront per (y, z) line of one chunk, lane
+// = right-hand side. Each lane keeps its right-hand side's K line points in registers and
+// adds, from every atom whose y-z stencil covers the line (the setup's line lists, in atom
+// order), the atom's P x-points with the arithmetic of k_spread:
+//   A = d_x w_y w_z,  B = d_y w'_y w_z + d_z w_y w'_z,  q = fma(w'_x, A, q), fma(w_x, B, q)
+// (d = Mu d in u, w = M_P, w' = M_P'), in the same per-point order, so the real line
+// equals k_spread's. The lane then packs the line as K/2 complex points, runs the
+// transform of k_fft_x_real<K, true> in registers and stores the half spectrum: the real
+// grid is never written and the separate x pass is not needed. A line-list entry packs the
+// atom and its stencil offsets along y and z: (s << 8) | (t_y << 4) | t_z.
+template <int K, int P>
+__global__ void __launch_bounds__(64)
+k_spread_xline(float* __restrict__ grid, GridDims gd, const Geometry geo,
+               const int* __restrict__ line_start, const int* __restrict__ line_atoms,
+               const int* __restrict__ base, const float* __restrict__ th,
+               const float* __restrict__ dth, const float* __restrict__ dv, int B) {
+  constexpr int BG = 64;
+  constexpr int M = K / 2;
+  const int lane = threadIdx.x;
+  const int nlines = gd.K2 * gd.K3;
+  // XCD-aware: each XCD takes a contiguous range of lines (work-groups are dealt to the
+  // 8 XCDs round-robin; gridDim.x is a multiple of 8), so the atoms of neighbouring
+  // lines, which share most of their dipoles, stay in one L2
+  const int per = gridDim.x / 8;
+  const int line = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (line >= nlines) return;  // uniform over the wavefront
+  const int chunk = blockIdx.y + gd.chunk0;
+  const int bg = chunk * BG + lane;
+  const float m00 = (float)geo.Mu[0][0], m01 = (float)geo.Mu[0][1], m02 = (float)geo.Mu[0][2];
+  const float m10 = (float)geo.Mu[1][0], m11 = (float)geo.Mu[1][1], m12 = (float)geo.Mu[1][2];
+  const float m20 = (float)geo.Mu[2][0], m21 = (float)geo.Mu[2][1], m22 = (float)geo.Mu[2][2];
+  // the lane's K line points in four register arrays of 32 (plain local arrays: a
+  // wave-uniform index then selects a register by indexed moves, not scratch memory)
+  float r0[32], r1[32], r2[32], r3[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) r0[i] = r1[i] = r2[i] = r3[i] = 0.f;
+  const int lo = line_start[line], hi = line_start[line + 1];
+  // atoms are taken NB at a time: their entries, dipoles, stencil bases and weights are
+  // all requested before the first of them is added, so the loads of a batch overlap.
+  // Entries, atoms and bases are the same for every lane; reading them through
+  // readfirstlane makes the register index below wave-uniform, so the compiler selects
+  // the line register by an indexed move instead of spilling the arrays to scratch
+  constexpr int NB = 4;
+  for (int a0 = lo; a0 < hi; a0 += NB) {
+    int sc[NB], ty[NB], tz[NB], bx[NB];
+    float e0[NB], e1[NB], e2[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int a = min(a0 + j, hi - 1);  // a batch's tail repeats the last atom, unused
+      const int e = __builtin_amdgcn_readfirstlane(line_atoms[a]);
+      sc[j] = e >> 8;
+      ty[j] = (e >> 4) & 15;
+      tz[j] = e & 15;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const float* d = dv + (size_t)sc[j] * 3 * B + bg;
+      e0[j] = d[0]; e1[j] = d[B]; e2[j] = d[2 * B];
+      bx[j] = __builtin_amdgcn_readfirstlane(base[3 * sc[j]]);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      if (a0 + j >= hi) break;  // uniform over the wavefront
+      const float* tp = th + (size_t)sc[j] * 3 * P;
+      const float* dp = dth + (size_t)sc[j] * 3 * P;
+      const float wy = tp[P + ty[j]], dwy = dp[P + ty[j]];
+      const float wz = tp[2 * P + tz[j]], dwz = dp[2 * P + tz[j]];
+      // dipole in u: (Mu d)_b
+      const float d0 = m00 * e0[j] + m01 * e1[j] + m02 * e2[j];
+      const float d1 = m10 * e0[j] + m11 * e1[j] + m12 * e2[j];
+      const float d2 = m20 * e0[j] + m21 * e1[j] + m22 * e2[j];
+      const float A = d0 * wy * wz;
+      const float Bc = d1 * dwy * wz + d2 * wy * dwz;
+#pragma unroll
+      for (int t = 0; t < P; ++t) {
+        int x = bx[j] - t;
+        if (x < 0) x += K;
+        const float wa = dp[t], wb = tp[t];
+        const int g = x >> 5, o = x & 31;
+        // the empty asm statements differ per branch, so the compiler does not merge the
+        // four updates into one through a pointer that selects the array, which would
+        // put the arrays in scratch memory
+        if (g == 0) {
+          r0[o] = fma(wb, Bc, fma(wa, A, r0[o]));
+          asm volatile("; line segment 0");
+        } else if (g == 1) {
+          r1[o] = fma(wb, Bc, fma(wa, A, r1[o]));
+          asm volatile("; line segment 1");
+        } else if (K > 64 && g == 2) {
+          r2[o] = fma(wb, Bc, fma(wa, A, r2[o]));
+          asm volatile("; line segment 2");
+        } else if (K > 96) {
+          r3[o] = fma(wb, Bc, fma(wa, A, r3[o]));
+          asm volatile("; line segment 3");
+        }
+      }
+    }
+  }
+  // the lane's real line, packed as K/2 complex points, and the transform of
+  // k_fft_x_real<K, true>
+  float zr[M], zi[M];
+#pragma unroll
+  for (int n = 0; n < M; ++n) {
+    const int xa = 2 * n, xb = 2 * n + 1;
+    zr[n] = xa < 32 ? r0[xa & 31] : xa < 64 ? r1[xa & 31] : xa < 96 ? r2[xa & 31] : r3[xa & 31];
+    zi[n] = xb < 32 ? r0[xb & 31] : xb < 64 ? r1[xb & 31] : xb < 96 ? r2[xb & 31] : r3[xb & 31];
+  }
+  constexpr TwTable<K> T{};
+  reg_stages<M, 0, true>(zr, zi);
+  float* g = grid + (size_t)chunk * gd.chunk_elems;
+  const size_t lbase = (size_t)line * gd.XS * BG;
+  float* gw = g + lbase;
+  const uint32_t lo_st = (uint32_t)lane;
+  const uint32_t stride = (uint32_t)BG;
+  at(gw, lo_st) = zr[0] + zi[0];
+  at(gw, lo_st + stride) = 0.f;
+  at(gw, lo_st + (uint32_t)(2 * M) * stride) = zr[0] - zi[0];
+  at(gw, lo_st + (uint32_t)(2 * M + 1) * stride) = 0.f;
+#pragma unroll
+  for (int k = 1; k < M; ++k) {
+    const float fer = 0.5f * (zr[k] + zr[M - k]), fei = 0.5f * (zi[k] - zi[M - k]);
+    const float forr = 0.5f * (zi[k] + zi[M - k]), foi = -0.5f * (zr[k] - zr[M - k]);
+    // W_K^k = cos - i sin
+    const float wr = T.c[k] * forr + T.s[k] * foi, wi = T.c[k] * foi - T.s[k] * forr;
+    at(gw, lo_st + (uint32_t)(2 * k) * stride) = fer + wr;
+    at(gw, lo_st + (uint32_t)(2 * k + 1) * stride) = fei + wi;
+  }
+}
+
 #define MBD_REG_SIZES(X) \
   X(8) X(10) X(12) X(16) X(18) X(20) X(24) X(30) X(32) X(36) X(40) X(48) X(50) X(54) \
   X(60) X(64) X(72) X(80) X(90) X(96) X(100) X(108) X(120) X(128)
@@ -684,6 +814,37 @@ void launch_fft_pass(const Geometry& geo, const SysBuffers& b, int B, int BG, in
     case 2: launch_pass<R, kZConv>(geo.K[2], grid, gd, nchunks, c2, c2 + Ksum, G, st); break;
     case 3: launch_pass<R, kYInv>(geo.K[1], grid, gd, nchunks, c1, c1 + Ksum, G, st); break;
     default: launch_pass<R, kXInv>(geo.K[0], grid, gd, nchunks, c0, c0 + Ksum, G, st); break;
+  }
+}
+
+// The spread of chunks [chunk0, chunk0 + nchunks) fused with their forward x pass, when
+// compiled for this case (float, 64 right-hand sides per chunk, p = 6, a register-FFT
+// length): returns false otherwise, and the caller runs k_spread and pass 0 instead.
+bool launch_spread_xline(const Geometry& geo, const SysBuffers& b, int B, int BG, int chunk0,
+                         int nchunks, hipStream_t st) {
+  if (BG != 64 || geo.p != 6 || !b.line_start) return false;
+  GridDims gd;
+  gd.K1 = geo.K[0];
+  gd.K2 = geo.K[1];
+  gd.K3 = geo.K[2];
+  gd.XS = geo.K[0] + 2;
+  gd.KX = geo.K[0] / 2 + 1;
+  gd.BG = BG;
+  gd.chunk_elems = (size_t)gd.K3 * gd.K2 * gd.XS * BG;
+  gd.chunk0 = chunk0;
+  const int nlines = gd.K2 * gd.K3;
+  dim3 grd((unsigned)((nlines + 7) / 8 * 8), nchunks);
+  switch (geo.K[0]) {
+#define MBD_SXL(KK)                                                                      \
+    case KK:                                                                             \
+      k_spread_xline<KK, 6><<<grd, 64, 0, st>>>((float*)b.grid, gd, geo, b.line_start,   \
+                                               b.line_atoms, b.base, (const float*)b.th, \
+                                               (const float*)b.dth, (const float*)b.dv, B); \
+      return true;
+    MBD_REG_SIZES(MBD_SXL)
+#undef MBD_SXL
+    default:
+      return false;
   }
 }
 

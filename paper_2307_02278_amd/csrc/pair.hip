@@ -407,6 +407,171 @@ k_pair_list(const Geometry geo, const int2* __restrict__ hdr, const R* __restric
   }  // groups of this work-group
 }
 
+// E_dir of a group on the matrix cores (float, B a multiple of 64). For the group's 16
+// targets t the field is one dense product over k = 3 c + b (candidate c, component b):
+//   E[t][a][rhs] = sum_k T_(c,t)[a][b] d_(j(c))[b][rhs],
+// the list's zero tensors standing for out-of-range (target, candidate) pairs. It is
+// computed as three 16-row tiles (a = x, y, z) times NT column tiles of 16 right-hand
+// sides with v_mfma_f32_16x16x4_f32, four rows of k per instruction: the instruction
+// takes A[i][k] from lane i + 16 k and B[k][j] from lane j + 16 k and leaves D[i][j] in
+// register i % 4 of lane j + 16 (i / 4). A wavefront owns 16 NT right-hand sides and
+// every NK-th block of four candidates (three steps of four k rows); the NK partial
+// products of a group are added in LDS
+// in wavefront order, so the result does not depend on timing. The source atoms of up
+// to kMfmaChunk candidates at a time are staged in LDS; each lane then reads its tensor
+// row and dipole component straight from global memory, one block of three steps ahead
+// of the matrix instructions that use them. With NK = 1 the k order is the vector
+// kernel's, and so far the two have given the same bits.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kMfmaChunk = 1024;  // candidates per LDS chunk (a multiple of 4)
+
+template <int NT>
+struct MfmaOperands {
+  float a[3];
+  float b[NT];
+};
+
+template <int NK, int NT, int NN>
+__global__ void __launch_bounds__(256)
+k_pair_mfma(const Geometry geo, const int2* __restrict__ hdr, const float* __restrict__ Tg,
+            const float* __restrict__ Tz, const int* __restrict__ gcount, int cap,
+            const float* __restrict__ dv, float* __restrict__ Ed, int B) {
+  // partial tiles of one component for the NK-way reduction: [wavefront][tile][lane]
+  // for the work-group's NN x NK wavefronts (NN column wavefronts)
+  __shared__ f32x4 red[NK > 1 ? NN * NK * NT * 64 : 1];
+  __shared__ int jl[kMfmaChunk];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wk = wave % NK, wn = wave / NK;
+  const int col = lane & 15, row = lane >> 4;
+  // column col of column tile t is right-hand side rhs + t: a lane's NT right-hand
+  // sides are contiguous, so its dipoles and results move as 16-byte vectors
+  const int rhs = wn * 16 * NT + NT * col;
+  const size_t Bs = (size_t)B;
+  // XCD-aware walk over groups, as in the vector list kernel
+  const int ngroups = (geo.n + kGroup - 1) / kGroup;
+  const int per = (ngroups + 7) / 8;
+  const int nbx = gridDim.x / 8;
+  for (int gi = blockIdx.x / 8; gi < per; gi += nbx) {
+    const int group = (blockIdx.x % 8) * per + gi;
+    if (group >= ngroups) return;  // uniform over the work-group
+    const int cnt = min(gcount[group], cap);
+    const int2* H = hdr + (size_t)group * cap;
+    const float* T = Tg + (size_t)group * cap * kCandStride;
+    f32x4 acc[3][NT];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[a][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int c0 = 0; c0 < cnt; c0 += kMfmaChunk) {
+      const int nc = min(kMfmaChunk, cnt - c0);
+      __syncthreads();  // the previous chunk's source atoms have been read
+      for (int c = threadIdx.x; c < nc; c += blockDim.x) jl[c] = H[c0 + c].x;
+      __syncthreads();
+      const float* Tc = T + (size_t)c0 * kCandStride;
+      // operands of one step: row b of the symmetric tensor (xx, yy, zz, xy, xz, yz) of
+      // candidate c and target col (b = 0: xx xy xz, b = 1: xy yy yz, b = 2: xz yz zz)
+      // and component b of the candidate's dipoles. Every load is issued: candidates
+      // past the chunk read the zero tensor Tz and the chunk's first dipoles, so no
+      // branch hides a load from the compiler's count of loads in flight.
+      auto load = [&](int c, int b, const int (&w)[3], MfmaOperands<NT>& o) {
+        const bool ok = c < nc;
+        const float* tt = ok ? Tc + ((size_t)c * kGroup + col) * kTensorWords : Tz;
+        const float4* dj =
+            reinterpret_cast<const float4*>(dv + ((size_t)jl[ok ? c : 0] * 3 + b) * Bs + rhs);
+        o.a[0] = tt[w[0]]; o.a[1] = tt[w[1]]; o.a[2] = tt[w[2]];
+#pragma unroll
+        for (int q = 0; q < NT / 4; ++q) {
+          const float4 v = dj[q];
+          o.b[4 * q] = v.x; o.b[4 * q + 1] = v.y; o.b[4 * q + 2] = v.z; o.b[4 * q + 3] = v.w;
+        }
+      };
+      auto apply = [&](const MfmaOperands<NT>& o) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            acc[a][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a[a], o.b[t], acc[a][t], 0, 0, 0);
+      };
+      // The work comes in blocks of 4 candidates = 12 rows of k = 3 steps, and the
+      // wavefront takes blocks p = wk, wk + NK, ...: lane row r of step u of block p has
+      // k = 12 p + 4 u + r, so its candidate 4 p + (4 u + r) / 3 and component
+      // (4 u + r) % 3 are fixed per lane and step. The operands of the next block are in
+      // flight while the matrix instructions of this one run.
+      int cu[3], bu[3], wu[3][3];
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        const int kq = 4 * u + row;
+        cu[u] = kq / 3;
+        bu[u] = kq % 3;
+        wu[u][0] = bu[u] == 0 ? 0 : bu[u] == 1 ? 3 : 4;
+        wu[u][1] = bu[u] == 0 ? 3 : bu[u] == 1 ? 1 : 5;
+        wu[u][2] = bu[u] == 0 ? 4 : bu[u] == 1 ? 5 : 2;
+      }
+      const int nb = (nc + 3) / 4;
+      const int m = wk < nb ? (nb - wk + NK - 1) / NK : 0;  // this wavefront's blocks
+      MfmaOperands<NT> buf[3];
+#pragma unroll
+      for (int u = 0; u < 3; ++u) load(4 * wk + cu[u], bu[u], wu[u], buf[u]);
+      for (int i = 0; i < m; ++i) {
+        const int cn = 4 * (wk + NK * (i + 1));  // first candidate of the next block
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          apply(buf[u]);
+          load(cn + cu[u], bu[u], wu[u], buf[u]);
+          // keep each step's instructions together: interleaving the accumulator chains
+          // of neighbouring steps makes the register allocator double the accumulators
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    }
+    // D[i][j] in register i % 4 of lane j + 16 (i / 4): target 4 row + r, column col;
+    // the lane's four right-hand sides rhs + 4 q .. rhs + 4 q + 3 of component a
+    auto store = [&](int a, int q, const f32x4 (&v)[4]) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = group * kGroup + 4 * row + r;
+        if (i < geo.n)
+          *reinterpret_cast<float4*>(Ed + ((size_t)i * 3 + a) * Bs + rhs + 4 * q) =
+              make_float4(v[0][r], v[1][r], v[2][r], v[3][r]);
+      }
+    };
+    if constexpr (NK == 1) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int q = 0; q < NT / 4; ++q) {
+          const f32x4 v[4] = {acc[a][4 * q], acc[a][4 * q + 1], acc[a][4 * q + 2],
+                              acc[a][4 * q + 3]};
+          store(a, q, v);
+        }
+    } else {
+      // one component at a time: every wavefront leaves its partial tiles in LDS, then
+      // wavefront wk adds the NK partials of the quads q = wk, wk + NK, ... in wavefront
+      // order and stores them
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        __syncthreads();  // the previous round's partials have been read
+#pragma unroll
+        for (int t = 0; t < NT; ++t) red[((wn * NK + wk) * NT + t) * 64 + lane] = acc[a][t];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NT / 4; ++q) {
+          if (q % NK != wk) continue;
+          f32x4 v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            v[u] = red[((wn * NK) * NT + 4 * q + u) * 64 + lane];
+#pragma unroll
+            for (int w = 1; w < NK; ++w) v[u] += red[((wn * NK + w) * NT + 4 * q + u) * 64 + lane];
+          }
+          store(a, q, v);
+        }
+      }
+    }
+  }  // groups of this work-group
+}
+
 
 // Direct-space part of the bilinear force term for one reverse step: with
 // p = g * lbar_k and q = g * y_k, dS/dR_t for S = sum_(t,j,n) p_t^T T_dir(r) q_j is
@@ -685,6 +850,34 @@ void launch_pair(const Geometry& g, const SysBuffers& b, int B, hipStream_t st) 
   const int nblk = pair_blocks(g, ngroups);
   const int2* H = b.pg_hdr;
   const R* T = (const R*)b.pg_T;
+  if constexpr (sizeof(R) == 4) {
+    // matrix cores: 128 right-hand sides per wavefront (64 when B = 64 or 192), B / 128
+    // column wavefronts x NK candidate shares per group (NK from pair_ns, at most 4
+    // wavefronts per work-group)
+    if (g.pair_mode == 1 && B % 64 == 0 && B <= 256) {
+      const int wide = B % 128 == 0 ? 128 : 64;
+      const int nn = B / wide;
+      int nk = g.pair_ns > 0 ? g.pair_ns : 1;
+      while (nk > 1 && nn * nk > 4) nk /= 2;
+      const dim3 blk(64 * nn * nk);
+      const float* Tf = (const float*)T;
+      const float* df = (const float*)dv;
+      float* Ef = (float*)Ed;
+#define MBD_PM(NK, NT, NN) \
+      k_pair_mfma<NK, NT, NN><<<nblk, blk, 0, st>>>(g, H, Tf, (const float*)b.pg_zero, b.pg_count, \
+                                            b.pg_cap, df, Ef, B)
+      // (nk > 1 only with nn <= 2, and nn = 2 only with nk <= 2)
+      if (nk == 1) {
+        if (wide == 128) MBD_PM(1, 8, 1); else MBD_PM(1, 4, 1);
+      } else if (wide == 128) {
+        if (nk == 4) MBD_PM(4, 8, 1); else if (nn == 1) MBD_PM(2, 8, 1); else MBD_PM(2, 8, 2);
+      } else {
+        if (nk == 4) MBD_PM(4, 4, 1); else MBD_PM(2, 4, 1);
+      }
+#undef MBD_PM
+      return;
+    }
+  }
   const int ns = pair_subsets(g, ngroups, B);
 #define MBD_PL(NS, WP) \
   k_pair_list<R, NS, WP><<<nblk, 64 * WP, 0, st>>>(g, H, T, b.pg_count, b.pg_cap, dv, Ed, B)

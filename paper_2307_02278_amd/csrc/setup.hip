@@ -191,6 +191,28 @@ __global__ void k_tile_fill(Geometry geo, const int* __restrict__ base,
       }
 }
 
+// x-lines (y, z) covered by the y-z stencil of each atom: y = base_y - t_y, z = base_z - t_z
+// (mod K), t = 0..P-1 (P distinct lines per axis, since K >= 2P). First a count per
+// line, then, after a scan, the fill of entries (s << 8) | (t_y << 4) | t_z, whose order
+// is the atom order.
+template <int P>
+__global__ void k_line_lists(Geometry geo, const int* __restrict__ base, int* __restrict__ count,
+                             const int* __restrict__ start, int* __restrict__ list) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= geo.n) return;
+  for (int tz = 0; tz < P; ++tz) {
+    int z = base[3 * s + 2] - tz;
+    if (z < 0) z += geo.K[2];
+    for (int ty = 0; ty < P; ++ty) {
+      int y = base[3 * s + 1] - ty;
+      if (y < 0) y += geo.K[1];
+      const int line = z * geo.K[1] + y;
+      const int slot = atomicAdd(&count[line], 1);
+      if (start) list[start[line] + slot] = (s << 8) | (ty << 4) | tz;
+    }
+  }
+}
+
 // Deterministic order inside each tile's list.
 __global__ void k_sort_tiles(int ntiles, const int* __restrict__ start, int* __restrict__ list) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -259,6 +281,22 @@ void launch_setup(const Geometry& g, SysBuffers& b, const double* pos, const dou
       break;
   }
   k_sort_tiles<<<blocks_for(ntiles, 128), 128, 0, st>>>(ntiles, b.tile_start, b.tile_atoms);
+  if (g.line_lists) launch_line_lists(g, b, st);
+}
+
+// Atoms of every (y, z) grid line for the fused x-line spread (p = 6), in atom order.
+void launch_line_lists(const Geometry& g, SysBuffers& b, hipStream_t st) {
+  if (b.line_start && g.p == 6) {
+    const int nlines = g.K[1] * g.K[2];
+    fill_int(b.line_count, 0, nlines + 1, st);
+    k_line_lists<6><<<blocks_for(g.n, 256), 256, 0, st>>>(g, b.base, b.line_count, nullptr,
+                                                          nullptr);
+    k_scan<<<1, 1024, 0, st>>>(nlines, b.line_count, b.line_start);
+    fill_int(b.line_count, 0, nlines + 1, st);
+    k_line_lists<6><<<blocks_for(g.n, 256), 256, 0, st>>>(g, b.base, b.line_count,
+                                                          b.line_start, b.line_atoms);
+    k_sort_tiles<<<blocks_for(nlines, 128), 128, 0, st>>>(nlines, b.line_start, b.line_atoms);
+  }
 }
 
 template void launch_setup<float>(const Geometry&, SysBuffers&, const double*, const double*,

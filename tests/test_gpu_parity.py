@@ -319,3 +319,121 @@ def test_energy_sd_matches_oracle_spread(tiny, graph):
     _, sd1 = one.execute(energy_sd=True)
     one.check()
     assert math.isnan(float(sd1[0]))
+
+
+@pytest.mark.parametrize("grid", [(18, 24, 30), (30, 20, 24), (50, 24, 30), (96, 20, 24)])
+@pytest.mark.parametrize("comp", [4, 15])
+def test_matvec_line_spread_fused_with_x_transform(grid, comp):
+    """The x-line spread fused with the forward x transform (64 right-hand sides per
+    chunk, float): unequal axes, odd and even half lengths of the packed x line, against
+    the oracle, and bit for bit against the tile spread followed by the x pass."""
+    import paper_2307_02278_amd as P
+    base = synth.tiny_random(seed=7, n=60)
+    cell = np.diag([10.0, 11.5, 13.0]) * A
+    pos = base.pos * np.array([1.0, 1.15, 1.3])
+    s = synth.System("ortho", pos, cell, base.alpha[:60], base.omega[:60], base.rvdw[:60])
+    ds = P.DeviceSystem(s.pos, s.cell, s.alpha, s.omega, s.rvdw)
+    out = []
+    for mode in (0, 1):
+        prm = P.Params(ewald_tau=0.35 * synth.BOHR_ANGSTROM, real_cutoff=13.0 * A, grid=grid,
+                       n_probes=64, n_steps=4, block=64, precision=P.PREC_MIXED,
+                       tune=P.TUNE_GIVEN, shape=dict(overlap=1, spread_mode=mode))
+        plan = P.Plan([ds], prm)
+        assert plan.info(0).shape.spread_mode == mode
+        v = torch.randn(64, s.n, 3, dtype=torch.float64,
+                        generator=torch.Generator().manual_seed(5))
+        out.append(plan.matvec(v.cuda(), components=comp).cpu())
+        if mode == 1:
+            op = _oracle_op(s, plan)
+            want = op(v.permute(1, 2, 0), comp).permute(2, 0, 1)
+            assert _err(out[1], want, f"line spread grid {grid} comp {comp}") < MIXED_TOL[comp]
+        plan.close()
+    diff = float((out[1] - out[0]).abs().max() / out[0].abs().max())
+    print(f"line spread vs tile spread: {diff:.2e}")
+    assert diff <= 1e-6
+
+
+def test_line_spread_on_a_general_cell():
+    """The fused line spread with the chain-rule matrix of a skewed cell."""
+    import paper_2307_02278_amd as P
+    s = synth.triclinic_random()
+    ds = P.DeviceSystem(s.pos, s.cell, s.alpha, s.omega, s.rvdw)
+    prm = P.Params(ewald_tau=0.35 * synth.BOHR_ANGSTROM, real_cutoff=13.0 * A,
+                   grid=(16, 18, 20), n_probes=64, n_steps=4, block=64, precision=P.PREC_MIXED,
+                   tune=P.TUNE_GIVEN, shape=dict(overlap=1, spread_mode=1))
+    plan = P.Plan([ds], prm)
+    v = torch.randn(64, s.n, 3, dtype=torch.float64, generator=torch.Generator().manual_seed(8))
+    got = plan.matvec(v.cuda()).cpu()
+    want = _oracle_op(s, plan)(v.permute(1, 2, 0)).permute(2, 0, 1)
+    assert _err(got, want, "line spread, skewed cell") < MIXED_TOL[15]
+
+
+@pytest.fixture(scope="module")
+def water600():
+    return synth.water_box(200, seed=11)
+
+
+@pytest.mark.parametrize("block,nk", [(64, 1), (64, 2), (64, 4), (128, 1), (128, 2), (128, 4), (256, 1),
+                                      (256, 2)])
+def test_matvec_matrix_core_pair_kernel(water600, block, nk):
+    """The direct-space sum on the matrix cores (dense per-group product over 16 targets
+    x 3 components, 600 atoms: 38 groups, the last one ragged, and candidate lists whose
+    3 x count is not a multiple of the 4 rows per instruction), against the oracle
+    element by element and against the vector list kernel to float32 rounding."""
+    import paper_2307_02278_amd as P
+    s = water600
+    ds = P.DeviceSystem(s.pos, s.cell, s.alpha, s.omega, s.rvdw)
+    v = torch.randn(block, s.n, 3, dtype=torch.float64,
+                    generator=torch.Generator().manual_seed(17))
+    got = {}
+    for mode in (0, 1):
+        prm = P.Params(real_cutoff=7.0 * A, grid=(24, 24, 24), n_probes=block, n_steps=4,
+                       block=block, precision=P.PREC_MIXED, tune=P.TUNE_GIVEN,
+                       shape=dict(overlap=1, pair_mode=mode, pair_subsets=nk if mode else 0))
+        plan = P.Plan([ds], prm)
+        assert plan.info(0).shape.pair_mode == mode
+        got[mode] = {c: plan.matvec(v.cuda(), components=c).cpu() for c in (2, 15)}
+        if mode == 1:
+            op = _oracle_op(s, plan)
+            for c in (2, 15):
+                want = op(v.permute(1, 2, 0), c).permute(2, 0, 1)
+                assert _err(got[1][c], want, f"matrix cores B={block} NK={nk} comp {c}") \
+                    < MIXED_TOL[c]
+        plan.check()
+        plan.close()
+    # two float32 summation orders of the same terms (the same bits when NK = 1)
+    d = _err(got[1][2], got[0][2], "matrix cores vs vector kernel")
+    assert d < MIXED_TOL[2]
+
+
+def test_matrix_core_pair_kernel_on_a_general_cell():
+    """The matrix-core direct sum with a skewed cell (several images per pair)."""
+    import paper_2307_02278_amd as P
+    s = synth.triclinic_random()
+    ds = P.DeviceSystem(s.pos, s.cell, s.alpha, s.omega, s.rvdw)
+    prm = P.Params(ewald_tau=0.35 * synth.BOHR_ANGSTROM, real_cutoff=13.0 * A,
+                   grid=(16, 18, 20), n_probes=64, n_steps=4, block=64, precision=P.PREC_MIXED,
+                   tune=P.TUNE_GIVEN, shape=dict(overlap=1, pair_mode=1, pair_subsets=2))
+    plan = P.Plan([ds], prm)
+    assert plan.info(0).shape.pair_mode == 1
+    v = torch.randn(64, s.n, 3, dtype=torch.float64, generator=torch.Generator().manual_seed(9))
+    op = _oracle_op(s, plan)
+    for c in (2, 15):
+        got = plan.matvec(v.cuda(), components=c).cpu()
+        want = op(v.permute(1, 2, 0), c).permute(2, 0, 1)
+        assert _err(got, want, f"matrix cores, skewed cell, comp {c}") < MIXED_TOL[c]
+    plan.check()
+
+
+def test_matrix_core_mode_falls_back_where_it_does_not_apply(tiny):
+    """pair_mode 1 is kept only for float tensors and blocks of 64, 128, 192 or 256."""
+    import paper_2307_02278_amd as P
+    ds = P.DeviceSystem(tiny.pos, tiny.cell, tiny.alpha, tiny.omega, tiny.rvdw)
+    for prec, block, want in ((P.PREC_MIXED, 32, 0), (P.PREC_FP64, 64, 0),
+                              (P.PREC_MIXED, 64, 1)):
+        prm = P.Params(real_cutoff=9.0 * A, grid=(0, 0, 0), n_probes=block, n_steps=3,
+                       block=block, precision=prec, tune=P.TUNE_GIVEN,
+                       shape=dict(overlap=1, pair_mode=1))
+        plan = P.Plan([ds], prm)
+        assert plan.info(0).shape.pair_mode == want
+        plan.close()

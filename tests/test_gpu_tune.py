@@ -2,8 +2,9 @@
 list-kernel residency, the lanes per target and the side stream for the pair kernel
 leave every result bit unchanged; the grid chunk width changes the order of the
 spread's and the gather's sums (sub-lanes share a stencil when fewer than 64 right-hand
-sides form a chunk) and the gather's work-group size the grouping of the partial sums of
-a_k, so results then agree to rounding. Every shape must match the
+sides form a chunk), the gather's work-group size the grouping of the partial sums of
+a_k and the matrix-core pair kernel (with its candidate split) the order of the
+direct-space sums, so results then agree to rounding. Every shape must match the
 oracle; a measured shape is stored in the cache file and taken from there by the next
 plan with the same key."""
 import json
@@ -42,7 +43,12 @@ SHAPES = [dict(pair_wg_per_cu=0, pair_subsets=0, grid_chunk=0, overlap=1),
           dict(pair_wg_per_cu=0, pair_subsets=2, grid_chunk=32, overlap=2),
           dict(pair_wg_per_cu=1, pair_subsets=4, grid_chunk=16, overlap=1),
           dict(pair_wg_per_cu=0, pair_subsets=0, grid_chunk=0, overlap=1, gather_waves=8),
-          dict(pair_wg_per_cu=2, pair_subsets=2, grid_chunk=64, overlap=2, gather_waves=8)]
+          dict(pair_wg_per_cu=2, pair_subsets=2, grid_chunk=64, overlap=2, gather_waves=8),
+          dict(pair_wg_per_cu=0, pair_subsets=0, grid_chunk=0, overlap=1, spread_mode=1),
+          dict(pair_wg_per_cu=3, pair_subsets=1, grid_chunk=0, overlap=0, spread_mode=1),
+          dict(pair_wg_per_cu=0, pair_subsets=1, grid_chunk=0, overlap=1, pair_mode=1),
+          dict(pair_wg_per_cu=2, pair_subsets=1, grid_chunk=0, overlap=2, pair_mode=1),
+          dict(pair_wg_per_cu=0, pair_subsets=2, grid_chunk=0, overlap=1, pair_mode=1)]
 
 
 def test_shapes_give_the_same_bits_and_match_the_oracle(water600):
@@ -56,13 +62,17 @@ def test_shapes_give_the_same_bits_and_match_the_oracle(water600):
         assert inf.shape_source == 3
         assert inf.shape.pair_subsets == sh["pair_subsets"]
         assert inf.shape.overlap == sh["overlap"]
+        assert inf.shape.spread_mode == sh.get("spread_mode", 0)
+        assert inf.shape.pair_mode == sh.get("pair_mode", 0)
         out = plan.matvec(v.cuda()).cpu()
         e, f = plan.execute(forces=True)
         plan.check()
+        mode = inf.shape.pair_mode
         res.append((out, e.cpu(), f.cpu(), (inf.shape.grid_chunk or 64,
-                                             inf.shape.gather_waves or 4)))
+                                             inf.shape.gather_waves or 4, mode,
+                                             inf.shape.pair_subsets if mode else 0)))
         plan.close()
-    # the same chunk width and gather work-group: the same bits
+    # the same chunk width, gather work-group and direct-space summation: the same bits
     for k in range(1, len(SHAPES)):
         same = [j for j in range(k) if res[j][3] == res[k][3]]
         for j in same[:1]:
@@ -104,11 +114,15 @@ def test_measured_shape_is_cached_and_reused(water600, tmp_path):
     second = _plan(s, P.TUNE_MEASURE, cache=cache)
     inf2 = second.info(0)
     assert inf2.shape_source == 2
-    for k in ("pair_wg_per_cu", "pair_subsets", "grid_chunk", "overlap", "gather_waves"):
+    for k in ("pair_wg_per_cu", "pair_subsets", "grid_chunk", "overlap", "gather_waves",
+              "spread_mode", "pair_mode"):
         assert getattr(inf2.shape, k) == getattr(inf.shape, k)
     e2 = second.execute()
     second.check()
-    assert torch.equal(e1, e0) and torch.equal(e2, e0)
+    # the cached shape gives the measured shape's bits; against the built-in shape the
+    # measured one may differ in summation order (chunk, gather group, matrix cores)
+    assert torch.equal(e2, e1)
+    assert float(e1[0]) == pytest.approx(float(e0[0]), rel=1e-6)
     assert len(open(cache).readlines()) == 1
     # another key (float64, block 16) is measured and appended
     third = _plan(s, P.TUNE_MEASURE, cache=cache, block=16, prec=0)
