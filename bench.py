@@ -33,7 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
-FP32_PEAK_TFLOPS = 157.3         # MI355X published FP32 vector peak (packed FMA)
+FP32_PEAK_TFLOPS = 157.3         # MI355X published FP32 peak (packed FMA and matrix cores)
 FP32_NONPACKED_TFLOPS = 78.6     # 256 CU x 64 FMA lanes x 2 flop x 2.4 GHz, no packed FP32
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 
@@ -42,15 +42,36 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Kernel instance behind each stage at the 24k workload (float, p = 6, 64-wide chunks,
-# B = 128: the list kernel runs two target subsets per wavefront and four wavefronts
-# per group).
+# Kernel instance behind each grid stage at the 24k workload (float, p = 6, 64-wide
+# chunks); the pair stage's instance depends on the shape (pair_kernel_name).
 STAGE_KERNEL = {
-    "pair": "k_pair_list<float, 2, 4>", "spread": "k_spread<float, 6, 64>",
+    "spread": "k_spread<float, 6, 64>",
     "fft_x": "k_fft_x_real<96, true>", "fft_y": "k_fft_reg<96, 1>",
     "fft_z_conv": "k_fft_reg<96, 2>", "ifft_y": "k_fft_reg<96, 3>",
     "ifft_x": "k_fft_x_real<96, false>", "gather": "k_gather_epilogue<float, 6, 64>",
 }
+
+
+def pair_kernel_name(shape, B, n_atoms):
+    """Instance of the direct-space list kernel that a float plan with this shape launches
+    for B right-hand sides (the launcher's rules in pair.hip)."""
+    ngroups = (n_atoms + 15) // 16
+    ns_given = shape.get("pair_subsets", 0)
+    if shape.get("pair_mode", 0) == 1 and B % 64 == 0 and B <= 256:
+        wide = 128 if B % 128 == 0 else 64
+        nn, nk = B // wide, ns_given or 1
+        while nk > 1 and nn * nk > 4:
+            nk //= 2
+        nt = 8 if wide == 128 else 4
+        nn_t = 2 if (nk == 2 and wide == 128 and nn == 2) else 1
+        return f"k_pair_mfma<{nk}, {nt}, {nn_t}>"
+    ns = 1 if B >= 64 else 64 // B
+    if ns_given > 0:
+        ns = max(ns, min(4, ns_given))
+    else:
+        while ns < 4 and ngroups * B * ns / 64 < 4096:
+            ns *= 2
+    return f"k_pair_list<float, {ns}, {B * ns // 64}>"
 
 
 def measured_traffic(kernel):
@@ -116,6 +137,9 @@ def median_ms(fn, reps, torch):
     return statistics.median(ts), out
 
 
+TUNE_CACHE = None  # --tune-cache: JSON-lines file of measured shapes (read and appended)
+
+
 def plan_for(P, synth, wl, forces, graph, tune, precision=None, shape=None, systems=None):
     A = synth.ANGSTROM_BOHR
     systems = systems or wl.systems
@@ -126,7 +150,7 @@ def plan_for(P, synth, wl, forces, graph, tune, precision=None, shape=None, syst
                    precision=P.PREC_MIXED if precision is None else precision,
                    seed=wl.probe_seed, want_forces=forces, graph=graph,
                    tune=(P.TUNE_GIVEN if shape else (P.TUNE_MEASURE if tune else P.TUNE_OFF)),
-                   shape=shape)
+                   shape=shape, tune_cache=TUNE_CACHE if tune else None)
     return ds, P.Plan(ds, prm)
 
 
@@ -349,6 +373,10 @@ def main():
     ap.add_argument("--reps", type=int, default=10,
                     help="graph replays per energy + forces median")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON-lines shape cache: measured shapes are stored there and later "
+                         "runs with the same key reuse them (e.g. counter runs, whose "
+                         "serialised dispatches would distort a fresh measurement)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 B=1 leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 1 GiB device copy first (reference for HBM byte counters)")
@@ -367,6 +395,8 @@ def main():
                     help="also run the Delta_11 convergence study (SPME vs grid, replica vs "
                          "cutoff) on a 216-water box and a 512-atom diamond box")
     args = ap.parse_args()
+    global TUNE_CACHE
+    TUNE_CACHE = args.tune_cache
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(probes would shard across GPUs with one final all-reduce).", file=sys.stderr)
@@ -449,7 +479,7 @@ def main():
     # Per-stage times: the same steps launched eagerly with HIP events around every
     # stage, on one stream (the tuned shape without the side stream), so that each
     # kernel's time is its own; not part of the value.
-    sh1 = {k: shape[k] for k in ("pair_wg_per_cu", "pair_subsets", "grid_chunk")}
+    sh1 = {k: v for k, v in shape.items() if k != "source"}
     sh1["overlap"] = 0
     _, splan = plan_for(P, synth, wl, forces=False, graph=False, tune=False, shape=sh1)
     splan.set_positions(pos)
@@ -478,17 +508,25 @@ def main():
                      if v[1] > 0 and k not in ("lanczos", "setup")}
     dom = max(kernel_stages, key=lambda k: kernel_stages[k][0])
     dom_ms_avg = kernel_stages[dom][0] / kernel_stages[dom][1]
+    pair_kernel = pair_kernel_name(shape, B, s.n)
     if dom == "pair":
         flops = 18.0 * n_pairs * B
         achieved = flops / (dom_ms_avg * 1e-3) / 1e12
-        roof = {"kernel": STAGE_KERNEL["pair"], "bound": "alu", "achieved": round(achieved, 3),
+        mfma = pair_kernel.startswith("k_pair_mfma")
+        roof = {"kernel": pair_kernel, "bound": "mfma" if mfma else "alu",
+                "achieved": round(achieved, 3),
                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                "traffic": measured_traffic(STAGE_KERNEL["pair"]),
-                "peak_nonpacked_fp32": FP32_NONPACKED_TFLOPS,
-                "frac_of_nonpacked_fp32": round(achieved / FP32_NONPACKED_TFLOPS, 4),
+                "traffic": measured_traffic(pair_kernel),
                 "avg_launch_ms": round(dom_ms_avg, 4),
                 "algorithmic_per_launch": f"18 flop x {n_pairs} pairs x {B} rhs"}
+        if mfma:
+            # the matrix cores also multiply the list's zero tensors (out-of-range
+            # target-candidate pairs of a 16-target group)
+            roof["peak_note"] = "FP32 matrix-core peak; algorithmic flops exclude zero tensors"
+        else:
+            roof["peak_nonpacked_fp32"] = FP32_NONPACKED_TFLOPS
+            roof["frac_of_nonpacked_fp32"] = round(achieved / FP32_NONPACKED_TFLOPS, 4)
     else:
         by = stage_bytes(dom, K, s.n, B // 2)
         achieved = by / (dom_ms_avg * 1e-3) / 1e9
@@ -498,6 +536,35 @@ def main():
                 "traffic": measured_traffic(STAGE_KERNEL.get(dom, "")),
                 "avg_launch_ms": round(dom_ms_avg, 4),
                 "algorithmic_per_launch": f"{by:.4g} B"}
+    # The pair kernel alone in its fastest stand-alone shape (matrix cores, four
+    # wavefronts per group, every group resident), timed the same way; the timed shape
+    # may run it narrower, to leave room for the grid stages beside it.
+    alone = None
+    if B % 64 == 0 and B <= 256:
+        sh_alone = dict(sh1, pair_mode=1, pair_subsets=4, pair_wg_per_cu=0, overlap=0)
+        _, aplan = plan_for(P, synth, wl, forces=False, graph=False, tune=False,
+                            shape=sh_alone)
+        aplan.set_positions(pos)
+        aplan.execute()
+        torch.cuda.synchronize()
+        aplan.stage_times()
+        aplan.set_timing(True)
+        for _ in range(args.steps):
+            aplan.set_positions(pos)
+            aplan.execute()
+        torch.cuda.synchronize()
+        aplan.set_timing(False)
+        aplan.check()
+        pst = aplan.stage_times()["pair"]
+        aplan.close()
+        a_ms = pst[0] / pst[1]
+        a_tf = 18.0 * n_pairs * B / (a_ms * 1e-3) / 1e12
+        alone = {"kernel": pair_kernel_name(sh_alone, B, s.n), "achieved": round(a_tf, 3),
+                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                 "frac": round(a_tf / FP32_PEAK_TFLOPS, 4), "avg_launch_ms": round(a_ms, 4),
+                 "shape": sh_alone}
+        log(f"pair kernel alone: {alone}")
+    roof["pair_kernel_alone"] = alone
     # Whole-matvec algorithmic bytes 24 K^3 + 48 N per probe-vector.
     bmv = 24.0 * K[0] * K[1] * K[2] + 48.0 * s.n
 
