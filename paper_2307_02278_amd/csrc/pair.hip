@@ -694,6 +694,170 @@ k_pair_force(const Geometry geo, const int2* __restrict__ hdr, const R* __restri
 }
 
 
+// The same direct force term on the matrix cores (float, B a multiple of 16, at most
+// 128). Summed over the right-hand sides, a pair's term needs only two 3x3 matrices,
+//   M1 = sum_rhs p_t q_j^T,  M2 = sum_rhs q_t p_j^T:
+//   X = tr M1 + tr M2,  (M1 + M1^T + M2 + M2^T) r = sum_rhs [p_t (q_j.r) + q_j (p_t.r)
+//   + q_t (p_j.r) + p_j (q_t.r)] =: m,  Y = r.m / 2,
+//   grad_r u = r (A'/r X - B'/r Y) - B m.
+// For a group's 16 targets and a block of 16 candidates, M1 and M2 are dense products
+// over the right-hand sides: 9 + 9 tiles of 16 x 16 (component pairs (a, b), rows =
+// targets, columns = candidates) with v_mfma_f32_16x16x4_f32 over k = right-hand side.
+// The order of k is free: in the u-th of four consecutive steps lane row kk takes right-
+// hand side 16 s + 4 kk + u, so that each lane reads its four values as one 16-byte
+// vector. The group's p_t and q_t sit in LDS for the whole group; the candidates' p_j and
+// q_j come from global memory one group of four steps ahead. After a block's last step
+// each lane holds M1 and M2 of the pairs (targets 4 kk .. 4 kk + 3, candidate lane % 16)
+// and adds their terms (in-range pairs only) to its float64 partial forces; the 16
+// candidate lanes, then the NK wavefronts of the group are summed in a fixed order and
+// the group's forces added to fsum (each group owns its targets: no atomics).
+template <int NK>
+__global__ void __launch_bounds__(64 * NK)
+k_pair_force_mfma(const Geometry geo, const int2* __restrict__ hdr, const float* __restrict__ Fg,
+                  const int* __restrict__ gcount, int cap, const float* __restrict__ pv,
+                  const float* __restrict__ qv, double* __restrict__ fsum, int B) {
+  constexpr int kMaxB = 128;
+  constexpr int RP = kMaxB + 4;  // padded row of one (vector, component, target) in LDS
+  __shared__ float4 tl4[2 * 3 * kGroup * RP / 4];  // [p|q][a][t][rhs]
+  __shared__ int jl[kMfmaChunk];
+  __shared__ int ml[kMfmaChunk];
+  __shared__ double red[NK][kGroup][3];
+  float* tl = reinterpret_cast<float*>(tl4);
+  const int lane = threadIdx.x & 63;
+  const int wk = threadIdx.x >> 6;
+  const int col = lane & 15, row = lane >> 4;
+  const size_t Bs = (size_t)B;
+  const int ngroups = (geo.n + kGroup - 1) / kGroup;
+  const int per = (ngroups + 7) / 8;
+  const int nbx = gridDim.x / 8;
+  for (int gi = blockIdx.x / 8; gi < per; gi += nbx) {
+    const int group = (blockIdx.x % 8) * per + gi;
+    if (group >= ngroups) return;  // uniform over the work-group
+    const int cnt = min(gcount[group], cap);
+    const int2* H = hdr + (size_t)group * cap;
+    const float* F = Fg + (size_t)group * cap * kCandStride;
+    __syncthreads();  // the previous group's LDS contents have been read
+    // the group's p_t and q_t: [x][a][t][rhs], zero for targets past the end
+    for (int e = threadIdx.x; e < 2 * 3 * kGroup * B; e += 64 * NK) {
+      const int r = e % B, t = (e / B) % kGroup, a = (e / (B * kGroup)) % 3, x = e / (B * kGroup * 3);
+      const int i = group * kGroup + t;
+      const float* src = x == 0 ? pv : qv;
+      tl[((x * 3 + a) * kGroup + t) * RP + r] = i < geo.n ? src[((size_t)i * 3 + a) * Bs + r] : 0.f;
+    }
+    double G[4][3];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) G[r][0] = G[r][1] = G[r][2] = 0.0;
+    for (int c0 = 0; c0 < cnt; c0 += kMfmaChunk) {
+      const int nc = min(kMfmaChunk, cnt - c0);
+      __syncthreads();  // the previous chunk's lists have been read
+      for (int c = threadIdx.x; c < nc; c += 64 * NK) {
+        const int2 h = H[c0 + c];
+        jl[c] = h.x;
+        ml[c] = h.y;
+      }
+      __syncthreads();
+      const int nb = (nc + 15) / 16;  // blocks of 16 candidates
+      for (int blk = wk; blk < nb; blk += NK) {
+        const int c = blk * 16 + col;  // this lane's candidate column
+        const bool ok = c < nc;
+        const int j = jl[ok ? c : 0];
+        const float4* pj4 = reinterpret_cast<const float4*>(pv + (size_t)j * 3 * Bs);
+        const float4* qj4 = reinterpret_cast<const float4*>(qv + (size_t)j * 3 * Bs);
+        f32x4 m1[9], m2[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) m1[q] = m2[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // candidate operands of the four steps of group s: components b of p_j and q_j at
+        // right-hand sides 16 s + 4 row .. + 3
+        float4 bp[3], bq[3];
+        auto load_b = [&](int s, float4 (&xp)[3], float4 (&xq)[3]) {
+          const int o = (s < B / 16 ? 4 * s + row : row);  // float4 index within a row
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            xp[b] = pj4[b * (Bs / 4) + o];
+            xq[b] = qj4[b * (Bs / 4) + o];
+          }
+        };
+        load_b(0, bp, bq);
+        for (int s = 0; s < B / 16; ++s) {
+          float4 np[3], nq[3];
+          load_b(s + 1, np, nq);
+          // target operands from LDS: components a of p_t and q_t, target col
+          float4 ap[3], aq[3];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            ap[a] = *reinterpret_cast<const float4*>(&tl[((0 * 3 + a) * kGroup + col) * RP + 16 * s + 4 * row]);
+            aq[a] = *reinterpret_cast<const float4*>(&tl[((1 * 3 + a) * kGroup + col) * RP + 16 * s + 4 * row]);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+              for (int b = 0; b < 3; ++b) {
+                m1[3 * a + b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ap[a][u], bq[b][u], m1[3 * a + b], 0, 0, 0);
+                m2[3 * a + b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq[a][u], bp[b][u], m2[3 * a + b], 0, 0, 0);
+              }
+          }
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            bp[b] = np[b];
+            bq[b] = nq[b];
+          }
+        }
+        // the block's pairs (target 4 row + r, candidate c): D[i][j] sits in register
+        // i % 4 of lane j + 16 (i / 4)
+        const uint32_t msk = ok ? (uint32_t)ml[c] : 0u;
+        const float* f = F + ((size_t)(c0 + (ok ? c : 0)) * kGroup + 4 * row) * kTensorWords;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (!((msk >> (4 * row + r)) & 1u)) continue;
+          const float rx = f[6 * r], ry = f[6 * r + 1], rz = f[6 * r + 2];
+          const float Bk = f[6 * r + 3], c1 = f[6 * r + 4], c2 = f[6 * r + 5];
+          float M[3][3];
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) M[a][b] = m1[3 * a + b][r] + m2[3 * a + b][r];
+          const float X = M[0][0] + M[1][1] + M[2][2];
+          const float mx = (M[0][0] + M[0][0]) * rx + (M[0][1] + M[1][0]) * ry + (M[0][2] + M[2][0]) * rz;
+          const float my = (M[1][0] + M[0][1]) * rx + (M[1][1] + M[1][1]) * ry + (M[1][2] + M[2][1]) * rz;
+          const float mz = (M[2][0] + M[0][2]) * rx + (M[2][1] + M[1][2]) * ry + (M[2][2] + M[2][2]) * rz;
+          const float Y = 0.5f * (rx * mx + ry * my + rz * mz);
+          const float sc = c1 * X - c2 * Y;
+          G[r][0] -= (double)(sc * rx - Bk * mx);
+          G[r][1] -= (double)(sc * ry - Bk * my);
+          G[r][2] -= (double)(sc * rz - Bk * mz);
+        }
+      }
+    }
+    // sum over the 16 candidate lanes of each row, then over the wavefronts in order
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        double v = G[r][a];
+        for (int off = 1; off < 16; off <<= 1) v += __shfl_xor(v, off);
+        G[r][a] = v;
+      }
+    if (col == 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) red[wk][4 * row + r][a] = G[r][a];
+    }
+    __syncthreads();
+    if (threadIdx.x < kGroup * 3) {
+      const int t = threadIdx.x / 3, a = threadIdx.x % 3;
+      double v = 0.0;
+#pragma unroll
+      for (int w = 0; w < NK; ++w) v += red[w][t][a];
+      const int i = group * kGroup + t;
+      if (i < geo.n) fsum[3 * (size_t)i + a] += v;
+    }
+  }  // groups of this work-group
+}
+
+
 // Replica method (eq. replica): E_i = sum over images n and atoms j with
 // |R_j + n - R_i| < R_cut, except (j = i, n = 0), of f T(r) d_j, the damped bare tensor
 // (A = f / r^3, B = 3 f / r^5). Float64, any B <= 8 right-hand sides. One work-group
@@ -915,6 +1079,15 @@ void launch_pair_force(const Geometry& g, const SysBuffers& b, int B, hipStream_
   const R* F = (const R*)b.pg_F;
   const R* p = (const R*)b.dv;
   const R* q = (const R*)b.dq;
+  if constexpr (sizeof(R) == 4) {
+    // matrix cores, with the matrix-core direct sum: four wavefronts per group
+    if (g.pair_mode == 1 && B % 16 == 0 && B <= 128) {
+      k_pair_force_mfma<4><<<pair_blocks(g, ngroups), 256, 0, st>>>(
+          g, H, (const float*)F, b.pg_count, b.pg_cap, (const float*)p, (const float*)q,
+          b.fsum + 3 * (size_t)g.n, B);
+      return;
+    }
+  }
   // right-hand-side slices of 64 (or target subsets when B < 64), then target splits
   // over 1-4 wavefronts until the launch has 4096 wavefronts
   const int rs = B >= 64 ? B / 64 : 1;
