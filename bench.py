@@ -148,7 +148,7 @@ def plan_for(P, synth, wl, forces, graph, tune, precision=None, shape=None, syst
     prm = P.Params(real_cutoff=wl.real_cutoff_angstrom * A, grid=grid, n_probes=wl.n_probes,
                    n_steps=wl.n_steps, block=wl.block,
                    precision=P.PREC_MIXED if precision is None else precision,
-                   seed=wl.probe_seed, want_forces=forces, graph=graph,
+                   seed=wl.probe_seed, want_forces=forces, store_grids=forces, graph=graph,
                    tune=(P.TUNE_GIVEN if shape else (P.TUNE_MEASURE if tune else P.TUNE_OFF)),
                    shape=shape, tune_cache=TUNE_CACHE if tune else None)
     return ds, P.Plan(ds, prm)
@@ -189,7 +189,9 @@ def energy_forces_leg(P, torch, synth, name, graph, reps, fp64_check=False, gold
            "execution": "hip_graph_replay" if graph else "eager", "replays": reps,
            "energy_forces_ms": round(t_ef, 2), "energy_only_ms": round(t_e, 2),
            "plan_create_s": round(t_plan, 2), "forces_finite": bool(torch.isfinite(f).all()),
-           "shape": shape_of(P, plan)}
+           "shape": shape_of(P, plan), "store_grids": True,
+           "workspace_gib": round(sum(plan.info(k).workspace_bytes
+                                      for k in range(len(wl.systems))) / 2**30, 2)}
     if len(wl.systems) == 1:
         out["energy_ha"] = float(e[0])
         out["energy_sd_ha"] = float(sd[0])

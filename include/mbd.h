@@ -167,6 +167,11 @@ typedef struct {
                            one object per line keyed by device architecture, N, grid,
                            block, precision and forces; read at plan creation and
                            appended with each new measurement. NULL => no file.         */
+  int32_t store_grids;  /* with want_forces: 1 => keep the real potential grids of every
+                           forward Lanczos step of a probe block (n_steps x the grid
+                           bytes, e.g. 22.7 GB at N = 24k, K = 96, block 128), so that the
+                           reverse force terms read phi of y_k instead of running one
+                           more spread and transform per step; 0 => recompute them      */
 } mbd_params;
 
 /* Values derived on the host for one system of a plan. */

@@ -68,6 +68,7 @@ class MbdParams(C.Structure):
         ("tune", C.c_int32),
         ("shape", MbdShape),
         ("tune_cache", C.c_char_p),
+        ("store_grids", C.c_int32),
     ]
 
 

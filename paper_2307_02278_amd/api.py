@@ -34,6 +34,7 @@ class Params:
     shape: Optional[dict] = None    # TUNE_GIVEN: mbd_shape fields (pair_wg_per_cu, pair_subsets,
     #                                 grid_chunk, overlap, gather_waves, spread_mode, pair_mode)
     tune_cache: Optional[str] = None  # TUNE_MEASURE: JSON-lines cache file
+    store_grids: bool = False       # forces: keep the forward steps' potential grids
 
     def to_c(self) -> L.MbdParams:
         p = L.MbdParams()
@@ -62,6 +63,7 @@ class Params:
             setattr(p.shape, k, int(v))
         self._cache_bytes = self.tune_cache.encode() if self.tune_cache else None
         p.tune_cache = self._cache_bytes
+        p.store_grids = 1 if self.store_grids else 0
         return p
 
 

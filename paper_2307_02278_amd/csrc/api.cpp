@@ -198,6 +198,8 @@ void allocate_system(Plan& plan, System& S, int R_probes, int m) {
     b.abar = dalloc<double>(plan, (size_t)B * m, by);
     b.bbar = dalloc<double>(plan, (size_t)B * m, by);
     b.adj = dalloc<double>(plan, (size_t)B * 16, by);
+    if (plan.prm.store_grids)
+      b.phi = dalloc<R>(plan, (size_t)m * g.K[2] * g.K[1] * (g.K[0] + 2) * B, by);
     b.fsum = dalloc<double>(plan, 6 * (size_t)n, by);
   }
   if (plan.prm.krylov_block > 1) {
@@ -312,11 +314,13 @@ int spread_chunk(Plan& plan, System& S, const SysBuffers& b, int c, hipStream_t 
 // The adjoint matvec C lbar_k (into Lt) together with the bilinear force terms
 // lbar_k^T dC/dR y_k of one reverse step: the pair part, then per grid chunk the
 // reciprocal part with phi of p = g lbar_k (left by the matvec) and with phi of
-// q = g y_k (one more spread and transform of q). The pair kernel and the pair force
-// (into the direct half of fsum) run on the side stream beside the grid stages, forked
-// as in matvec_block.
+// q = g y_k. q is c9 g y_k with a per-right-hand-side factor c9 (b.adj[16 rhs + 9]), so
+// when the forward sweep kept its grids phi of q is c9 times the kept phi of step k,
+// and the factor moves onto p; otherwise q is spread and transformed once more. The
+// pair kernel and the pair force (into the direct half of fsum) run on the side stream
+// beside the grid stages, forked as in matvec_block.
 template <typename R>
-void adjoint_matvec_forces(Plan& plan, System& S) {
+void adjoint_matvec_forces(Plan& plan, System& S, int k) {
   const hipStream_t st = plan.stream;
   const int BG = S.BG;
   const int nch = plan.B / BG;
@@ -346,6 +350,15 @@ void adjoint_matvec_forces(Plan& plan, System& S) {
     });
     staged(plan, MBD_STAGE_FORCE,
            [&] { launch_spme_force<R>(S.geo, b, b.dq, plan.B, BG, c, st); });
+    if (b.phi) {
+      SysBuffers bk = b;
+      bk.grid = (R*)b.phi +
+                (size_t)k * S.geo.K[2] * S.geo.K[1] * (S.geo.K[0] + 2) * plan.B;
+      staged(plan, MBD_STAGE_FORCE, [&] {
+        launch_spme_force<R>(S.geo, bk, b.dv, plan.B, BG, c, st, b.adj + 9);
+      });
+      continue;
+    }
     const int fq = spread_chunk<R>(plan, S, bq, c, st);
     for (int pass = fq; pass < 5; ++pass)
       staged(plan, MBD_STAGE_FFT_X + pass,
@@ -370,7 +383,7 @@ void run_backward(Plan& plan, System& S, int l0, int nb) {
   for (int k = m - 1; k >= 0; --k) {
     staged(plan, MBD_STAGE_ADJOINT,
            [&] { launch_adjoint_step(S.geo, S.buf, B, nb, k, m, l0, fl, st); });
-    adjoint_matvec_forces<R>(plan, S);
+    adjoint_matvec_forces<R>(plan, S, k);
     staged(plan, MBD_STAGE_ADJOINT, [&] { launch_adjoint_accumulate(S.geo, S.buf, B, k, st); });
   }
 }
@@ -383,7 +396,8 @@ void run_backward(Plan& plan, System& S, int l0, int nb) {
 // HBM-bound grid stages, forked before the spreads (1) or after them, beside the
 // transforms only (2), and joined before the gathers.
 template <typename R>
-void matvec_block(Plan& plan, System& S, const double* w, uint32_t comps) {
+void matvec_block(Plan& plan, System& S, const double* w, uint32_t comps,
+                  void* phi_out = nullptr) {
   const hipStream_t st = plan.stream;
   const int BG = S.BG;
   const int nch = plan.B / BG;
@@ -409,6 +423,12 @@ void matvec_block(Plan& plan, System& S, const double* w, uint32_t comps) {
       for (int pass = first; pass < 5; ++pass)
         staged(plan, MBD_STAGE_FFT_X + pass,
                [&] { launch_fft_pass<R>(S.geo, S.buf, plan.B, BG, c, 1, pass, st); });
+  // the step's potential grids, kept for the reverse force terms
+  if (rec && phi_out)
+    staged(plan, MBD_STAGE_FFT_X + 4, [&] {
+      const size_t elems = (size_t)S.geo.K[2] * S.geo.K[1] * (S.geo.K[0] + 2) * plan.B;
+      copy_floats((float*)phi_out, (const float*)S.buf.grid, elems * sizeof(R) / 4, st);
+    });
   if (sd) join_side(st, sd->side, sd->pair_done);
   for (int c = 0; c < nch; ++c)
     staged(plan, MBD_STAGE_GATHER,
@@ -463,8 +483,10 @@ void run_energy(Plan& plan, System& S, int sys_index, double* energy, double* sd
       launch_init_scalars(S.buf, nb, m, l0, st);
       launch_probes(S.geo, S.buf, B, nb, l0, plan.prm.seed, sys_index, fl, st);
     });
+    const size_t gsz = (size_t)S.geo.K[2] * S.geo.K[1] * (S.geo.K[0] + 2) * B;
     for (int k = 0; k < m; ++k) {
-      matvec_block<R>(plan, S, S.buf.W + (size_t)k * vs, MBD_C_ALL);
+      void* slot = (forces && S.buf.phi) ? (void*)((R*)S.buf.phi + (size_t)k * gsz) : nullptr;
+      matvec_block<R>(plan, S, S.buf.W + (size_t)k * vs, MBD_C_ALL, slot);
       staged(plan, MBD_STAGE_LANCZOS, [&] {
         launch_finish_a(S.buf, B, nb, k, m, l0, plan.status, st);
         if (k + 1 < m) {

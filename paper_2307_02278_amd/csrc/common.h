@@ -157,6 +157,7 @@ struct SysBuffers {
   double* ybar = nullptr;      // [3][n][3][B] adjoints of y_{k+1}, y_k, y_{k-1} (rotating)
   double* lbar = nullptr;      // [n][3][B] adjoint of l_k (input of the adjoint matvec)
   void* dq = nullptr;          // Real [n][3][B] g * y_k
+  void* phi = nullptr;         // Real [m][K3][K2][K1 + 2][B]: the forward steps' potential grids
   double* tz = nullptr;        // [B][m][m] tridiagonal eigenvectors
   double* abar = nullptr;      // [B][m] dQ/da_k, then the full adjoint of a_k
   double* bbar = nullptr;      // [B][m] dQ/d nrm_k (k >= 1)
@@ -299,7 +300,9 @@ template <typename R>
 void launch_pair_force(const Geometry& g, const SysBuffers& b, int B, hipStream_t st);
 template <typename R>
 void launch_spme_force(const Geometry& g, const SysBuffers& b, const void* h, int B, int BG,
-                       int chunk0, hipStream_t st);
+                       int chunk0, hipStream_t st, const double* hscale = nullptr);
+// dst[0, n) = src[0, n) for 16-byte aligned real arrays (n a multiple of 4)
+void copy_floats(float* dst, const float* src, size_t n, hipStream_t st);
 void launch_tridiag_adjoint(const SysBuffers& b, int nb, int m, int probe0, uint32_t* status,
                             hipStream_t st);
 void launch_adjoint_step(const Geometry& g, const SysBuffers& b, int B, int nb, int k, int m,

@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(512)
 k_spme_force(const Geometry geo, const int* __restrict__ base, const R* __restrict__ th,
              const R* __restrict__ dth, const R* __restrict__ ddth, const R* __restrict__ grid,
              size_t chunk_elems, const R* __restrict__ hv, int B, int chunk0,
-             double* __restrict__ fsum) {
+             double* __restrict__ fsum, const double* __restrict__ hscale) {
   constexpr int NSUB = Lanes<BG>::NSUB;
   const int nw = blockDim.x >> 6;  // wavefronts per work-group (4 or 8)
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
@@ -360,7 +360,9 @@ k_spme_force(const Geometry geo, const int* __restrict__ base, const R* __restri
       }
     }
     const size_t o = (size_t)s * 3 * B + bg;
-    const R c0 = hv[o], c1 = hv[o + B], c2 = hv[o + 2 * B];
+    // h, times a per-right-hand-side factor when the grid belongs to a scaled dipole set
+    const R hs = hscale ? (R)hscale[(size_t)bg * 16] : R(1);
+    const R c0 = hs * hv[o], c1 = hs * hv[o + B], c2 = hs * hv[o + 2 * B];
     // Hessian in u: H_R = Mu^T H_u Mu, applied as Mu^T (H_u (Mu h))
     const R h0 = (R)geo.Mu[0][0] * c0 + (R)geo.Mu[0][1] * c1 + (R)geo.Mu[0][2] * c2;
     const R h1 = (R)geo.Mu[1][0] * c0 + (R)geo.Mu[1][1] * c1 + (R)geo.Mu[1][2] * c2;
@@ -450,14 +452,14 @@ void launch_epilogue(const Geometry& geo, const SysBuffers& b, const double* w, 
 
 template <typename R>
 void launch_spme_force(const Geometry& geo, const SysBuffers& b, const void* h, int B, int BG,
-                       int chunk0, hipStream_t st) {
+                       int chunk0, hipStream_t st, const double* hscale) {
   const size_t chunk = (size_t)geo.K[2] * geo.K[1] * (geo.K[0] + 2) * BG;
   dim3 grd(kRedBlocks, 1);
 #define MBD_SF(PP, BB)                                                                      \
   k_spme_force<R, PP, BB><<<grd, 64 * gather_waves(geo), 0, st>>>(                       \
       geo, b.base, (const R*)b.th, (const R*)b.dth,                                         \
                                                (const R*)b.ddth, (const R*)b.grid, chunk,     \
-                                               (const R*)h, B, chunk0, b.fsum)
+                                               (const R*)h, B, chunk0, b.fsum, hscale)
 #define MBD_SF_P(BB)                 \
   switch (geo.p) {                   \
     case 4: MBD_SF(4, BB); break;    \
@@ -478,9 +480,9 @@ void launch_spme_force(const Geometry& geo, const SysBuffers& b, const void* h, 
 }
 
 template void launch_spme_force<float>(const Geometry&, const SysBuffers&, const void*, int, int,
-                                       int, hipStream_t);
+                                       int, hipStream_t, const double*);
 template void launch_spme_force<double>(const Geometry&, const SysBuffers&, const void*, int,
-                                        int, int, hipStream_t);
+                                        int, int, hipStream_t, const double*);
 
 template void launch_spread<float>(const Geometry&, const SysBuffers&, int, int, int, int,
                                    hipStream_t);

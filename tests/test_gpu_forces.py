@@ -199,3 +199,37 @@ def test_matrix_core_forces_match_vector_forces(block):
     print(f"matrix-core vs vector forces, B={block}: {err:.2e} of max |F|")
     assert err <= 1e-5, err
     assert out[1][0] == pytest.approx(out[0][0], rel=1e-6)
+
+
+@pytest.mark.parametrize("prec,block,mode", [(0, 8, 0), (1, 16, 0), (1, 64, 1)])
+def test_kept_forward_grids_give_the_same_forces(tiny, prec, block, mode):
+    """store_grids: the reverse force terms read the forward steps' potential grids
+    (phi of y_k, scaled per right-hand side) instead of spreading and transforming
+    q = c9 g y_k again. Same energy bits; forces to the precision's bound, and against
+    the oracle."""
+    import paper_2307_02278_amd as P
+    R, m = 16 if block < 64 else 64, 10
+    ds = P.DeviceSystem(tiny.pos, tiny.cell, tiny.alpha, tiny.omega, tiny.rvdw)
+    out = []
+    for keep in (False, True):
+        prm = P.Params(ewald_tau=0.35 * synth.BOHR_ANGSTROM, real_cutoff=13.0 * A,
+                       grid=(16, 16, 16), n_probes=R, n_steps=m, block=block, precision=prec,
+                       seed=SEED, want_forces=True, store_grids=keep, tune=P.TUNE_GIVEN,
+                       shape=dict(overlap=1, pair_mode=mode, pair_subsets=4 if mode else 0))
+        plan = P.Plan([ds], prm)
+        e, f = plan.execute(forces=True)
+        e2, f2 = plan.execute(forces=True)  # the kept grids are rewritten each run
+        plan.check()
+        assert torch.equal(f, f2)
+        out.append((e.cpu(), f.cpu()))
+        if keep:
+            _, f_ref = _oracle_forces(tiny, plan, R, m)
+        plan.close()
+    assert torch.equal(out[0][0], out[1][0])
+    err = float((out[1][1] - out[0][1]).abs().max()) / float(out[0][1].abs().max())
+    tol = 1e-12 if prec == 0 else 1e-5
+    print(f"kept grids vs recomputed, prec {prec}, block {block}: {err:.2e} of max |F|")
+    assert err <= tol, err
+    oerr = float((out[1][1] - f_ref).abs().max()) / float(f_ref.abs().max())
+    print(f"kept grids vs oracle: {oerr:.2e}")
+    assert oerr <= (1e-7 if prec == 0 else 1e-5), oerr
