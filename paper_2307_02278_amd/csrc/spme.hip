@@ -317,12 +317,11 @@ k_spme_force(const Geometry geo, const int* __restrict__ base, const R* __restri
     const R* tp = th + (size_t)s * 3 * P;
     const R* dp = dth + (size_t)s * 3 * P;
     const R* ddp = ddth + (size_t)s * 3 * P;
-    R mx[P], dmx[P], ddmx[P], my[P], dmy[P], ddmy[P], mz[P], dmz[P], ddmz[P];
+    R mx[P], dmx[P], ddmx[P], my[P], dmy[P], ddmy[P];
 #pragma unroll
     for (int t = 0; t < P; ++t) {
       mx[t] = tp[t]; dmx[t] = dp[t]; ddmx[t] = ddp[t];
       my[t] = tp[P + t]; dmy[t] = dp[P + t]; ddmy[t] = ddp[P + t];
-      mz[t] = tp[2 * P + t]; dmz[t] = dp[2 * P + t]; ddmz[t] = ddp[2 * P + t];
     }
     const int bx = base[3 * s], by = base[3 * s + 1], bz = base[3 * s + 2];
     int kxs[P];
@@ -333,8 +332,11 @@ k_spme_force(const Geometry geo, const int* __restrict__ base, const R* __restri
       kxs[t1] = k1 * BG + b;
     }
     R hxx = R(0), hyy = R(0), hzz = R(0), hxy = R(0), hxz = R(0), hyz = R(0);
-#pragma unroll
+    // one z plane of the stencil at a time (not unrolled: unrolled, the compiler keeps
+    // all p^3 grid values of an atom in flight and the kernel runs at 2 waves per SIMD)
+#pragma unroll 1
     for (int t3 = 0; t3 < P; ++t3) {
+      const R mz3 = tp[2 * P + t3], dmz3 = dp[2 * P + t3], ddmz3 = ddp[2 * P + t3];
       int k3 = bz - t3;
       if (k3 < 0) k3 += K3;
 #pragma unroll
@@ -351,12 +353,12 @@ k_spme_force(const Geometry geo, const int* __restrict__ base, const R* __restri
           s1 += dmx[t1] * phi;
           s2 += ddmx[t1] * phi;
         }
-        hxx += s2 * my[t2] * mz[t3];
-        hyy += s0 * ddmy[t2] * mz[t3];
-        hzz += s0 * my[t2] * ddmz[t3];
-        hxy += s1 * dmy[t2] * mz[t3];
-        hxz += s1 * my[t2] * dmz[t3];
-        hyz += s0 * dmy[t2] * dmz[t3];
+        hxx += s2 * my[t2] * mz3;
+        hyy += s0 * ddmy[t2] * mz3;
+        hzz += s0 * my[t2] * ddmz3;
+        hxy += s1 * dmy[t2] * mz3;
+        hxz += s1 * my[t2] * dmz3;
+        hyz += s0 * dmy[t2] * dmz3;
       }
     }
     const size_t o = (size_t)s * 3 * B + bg;
