@@ -693,13 +693,14 @@ void tune_system(Plan& plan, System& S, int sys_index) {
   const bool list = S.buf.pg_T != nullptr && S.geo.replica_cut <= 0.0;
   mbd_shape best = kBuiltinShape;
   apply_shape(plan, S, best);
-  double tbest = time_matvec<R>(plan, S, 3);
-  // a candidate replaces the best shape only when it is at least 1 % faster, so that
-  // timing noise does not pick residency caps or other knobs that do not pay
+  double tbest = time_matvec<R>(plan, S, 5);
+  // a candidate replaces the best shape only when it is at least 2 % faster (fastest of
+  // five timings each), so that timing noise does not pick residency caps or other
+  // knobs that do not pay once the matvecs are replayed from a graph
   auto trial = [&](const mbd_shape& sh) {
     apply_shape(plan, S, sh);
-    const double t = time_matvec<R>(plan, S, 3);
-    if (t < 0.99 * tbest) {
+    const double t = time_matvec<R>(plan, S, 5);
+    if (t < 0.98 * tbest) {
       tbest = t;
       best = S.shape;
     }
@@ -726,7 +727,7 @@ void tune_system(Plan& plan, System& S, int sys_index) {
     }
     // the matrix-core kernel with 4, 2 or 1 wavefronts per group's candidates (the widest
     // split first: it is the fastest alone, and beside the grid stages the three are
-    // usually within the 1 % margin)
+    // usually within the 2 % margin)
     if (plan.prec == MBD_PREC_MIXED && B % 64 == 0 && B <= 256)
       for (int nk : {4, 2, 1}) {
         if ((B / 64) * nk > 4) continue;
