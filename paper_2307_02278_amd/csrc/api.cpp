@@ -413,26 +413,23 @@ void matvec_block(Plan& plan, System& S, const double* w, uint32_t comps,
     });
   };
   const bool rec = (comps & MBD_C_REC) != 0;
+  // with phi_out the step's grids live in phi_out (kept for the reverse force terms)
+  SysBuffers bb = S.buf;
+  if (phi_out) bb.grid = phi_out;
   if ((comps & MBD_C_DIR) && (S.overlap != 2 || !rec)) pair_work();
   int first = 0;
   if (rec)
-    for (int c = 0; c < nch; ++c) first = spread_chunk<R>(plan, S, S.buf, c, st);
+    for (int c = 0; c < nch; ++c) first = spread_chunk<R>(plan, S, bb, c, st);
   if ((comps & MBD_C_DIR) && S.overlap == 2 && rec) pair_work();
   if (rec)
     for (int c = 0; c < nch; ++c)
       for (int pass = first; pass < 5; ++pass)
         staged(plan, MBD_STAGE_FFT_X + pass,
-               [&] { launch_fft_pass<R>(S.geo, S.buf, plan.B, BG, c, 1, pass, st); });
-  // the step's potential grids, kept for the reverse force terms
-  if (rec && phi_out)
-    staged(plan, MBD_STAGE_FFT_X + 4, [&] {
-      const size_t elems = (size_t)S.geo.K[2] * S.geo.K[1] * (S.geo.K[0] + 2) * plan.B;
-      copy_floats((float*)phi_out, (const float*)S.buf.grid, elems * sizeof(R) / 4, st);
-    });
+               [&] { launch_fft_pass<R>(S.geo, bb, plan.B, BG, c, 1, pass, st); });
   if (sd) join_side(st, sd->side, sd->pair_done);
   for (int c = 0; c < nch; ++c)
     staged(plan, MBD_STAGE_GATHER,
-           [&] { launch_epilogue<R>(S.geo, S.buf, w, plan.B, BG, c, 1, comps, st); });
+           [&] { launch_epilogue<R>(S.geo, bb, w, plan.B, BG, c, 1, comps, st); });
 }
 
 template <typename R>

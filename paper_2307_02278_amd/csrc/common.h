@@ -301,8 +301,6 @@ void launch_pair_force(const Geometry& g, const SysBuffers& b, int B, hipStream_
 template <typename R>
 void launch_spme_force(const Geometry& g, const SysBuffers& b, const void* h, int B, int BG,
                        int chunk0, hipStream_t st, const double* hscale = nullptr);
-// dst[0, n) = src[0, n) for 16-byte aligned real arrays (n a multiple of 4)
-void copy_floats(float* dst, const float* src, size_t n, hipStream_t st);
 void launch_tridiag_adjoint(const SysBuffers& b, int nb, int m, int probe0, uint32_t* status,
                             hipStream_t st);
 void launch_adjoint_step(const Geometry& g, const SysBuffers& b, int B, int nb, int k, int m,

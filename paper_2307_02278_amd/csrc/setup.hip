@@ -239,19 +239,6 @@ __global__ void k_fill_int(int* __restrict__ p, int v, int n) {
 }  // namespace
 
 // Kernel-based clear (kept out of hipMemsetAsync so that the sequence can be captured).
-__global__ void k_copy4(float4* __restrict__ dst, const float4* __restrict__ src, size_t n4) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
-       i += (size_t)gridDim.x * blockDim.x)
-    dst[i] = src[i];
-}
-
-void copy_floats(float* dst, const float* src, size_t n, hipStream_t st) {
-  const size_t n4 = n / 4;
-  const unsigned blocks = (unsigned)std::min<size_t>((n4 + 255) / 256, 8192);
-  k_copy4<<<blocks, 256, 0, st>>>(reinterpret_cast<float4*>(dst),
-                                  reinterpret_cast<const float4*>(src), n4);
-}
-
 void fill_int(int* p, int v, int n, hipStream_t st) {
   k_fill_int<<<blocks_for(n, 256), 256, 0, st>>>(p, v, n);
 }
