@@ -56,7 +56,8 @@ def _mixed_plan(wl, forces=False, prec=None, tune=True, systems=None):
     prm = P.Params(real_cutoff=wl.real_cutoff_angstrom * A, grid=grid, n_probes=wl.n_probes,
                    n_steps=wl.n_steps, block=wl.block,
                    precision=P.PREC_MIXED if prec is None else prec, seed=wl.probe_seed,
-                   want_forces=forces, tune=P.TUNE_MEASURE if tune else P.TUNE_OFF)
+                   want_forces=forces, store_grids=forces,
+                   tune=P.TUNE_MEASURE if tune else P.TUNE_OFF)
     return ds, P.Plan(ds, prm)
 
 
@@ -193,6 +194,50 @@ def test_fullsize_forces_match_directional_derivative(forces_case):
     plan.set_positions(pos)
     slope = -(es[0] - es[1]) / (2.0 * h)
     assert slope == pytest.approx(fn, rel=2e-3), (slope, fn)
+
+
+def test_fullsize_24k_energy_and_forces():
+    """The 24k box in the bench's energy + forces configuration (128 probes x 50 steps,
+    forces, kept forward grids, measured shape, graph replay): per-probe quadrature
+    against the golden, replay against eager, and along u = F/|F| the central difference
+    of the GPU energy equals |F| (a property that holds at any size)."""
+    import paper_2307_02278_amd as P
+    wl = synth.workload("batched24k")
+    s = wl.systems[0]
+    ds = P.DeviceSystem(s.pos, s.cell, s.alpha, s.omega, s.rvdw)
+    out = {}
+    for graph in (False, True):
+        prm = P.Params(real_cutoff=wl.real_cutoff_angstrom * A, grid=(96, 96, 96),
+                       n_probes=wl.n_probes, n_steps=wl.n_steps, block=wl.block,
+                       precision=P.PREC_MIXED, seed=wl.probe_seed, want_forces=True,
+                       store_grids=True, tune=P.TUNE_MEASURE, graph=graph)
+        plan = P.Plan([ds], prm)
+        e, f = plan.execute(forces=True)
+        e, f = plan.execute(forces=True)
+        plan.check()
+        out[graph] = (e.cpu(), f.cpu())
+        if graph:
+            gold = _golden("water24k_quadrature")
+            q = plan.quadrature(0)
+            probes = [int(x) for x in gold["probes"]]
+            rel = (q[probes] - torch.from_numpy(gold["q"])).abs() / torch.from_numpy(gold["q"]).abs()
+            print(f"24k E + F plan: quadrature vs golden {float(rel.max()):.2e}")
+            assert float(rel.max()) < 1e-5
+            pos = torch.as_tensor(s.pos, dtype=torch.float64, device="cuda")
+            fn = float(f.norm())
+            u = f / fn
+            h = 5e-3
+            es = []
+            for sgn in (1.0, -1.0):
+                plan.set_positions(pos + sgn * h * u)
+                es.append(float(plan.execute()[0]))
+                plan.check()
+            slope = -(es[0] - es[1]) / (2.0 * h)
+            print(f"24k: directional derivative {slope:.6e} vs |F| {fn:.6e}")
+            assert slope == pytest.approx(fn, rel=2e-3), (slope, fn)
+        plan.close()
+    assert torch.equal(out[True][0], out[False][0])
+    assert torch.equal(out[True][1], out[False][1])
 
 
 def _workload_plan(wl):
