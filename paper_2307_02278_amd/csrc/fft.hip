@@ -333,6 +333,13 @@ __device__ __forceinline__ void reg_stages(float (&xr)[K], float (&xi)[K]) {
   }
 }
 
+// Value of the lane whose index differs in bit 0, by a DPP quad permutation (quad_perm
+// 1,0,3,2): a register move inside each group of four lanes, without the LDS crossbar
+// that a general shuffle goes through.
+__device__ __forceinline__ float lane_xor1(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
+}
+
 // One column is split over a lane pair (h = lane & 1): lane h holds the decimated
 // samples x[2m + h], m < H = K/2, runs an H-point FFT in registers, and the pair
 // finishes with one radix-2 step exchanged through a lane shuffle:
@@ -347,7 +354,7 @@ __device__ __forceinline__ void pair_dit(float (&xr)[K / 2], float (&xi)[K / 2],
   constexpr TwTable<K> T{};
 #pragma unroll
   for (int k = 0; k < H; ++k) {
-    const float pr = __shfl_xor(xr[k], 1), pi = __shfl_xor(xi[k], 1);
+    const float pr = lane_xor1(xr[k]), pi = lane_xor1(xi[k]);
     const float er = h ? pr : xr[k], ei = h ? pi : xi[k];
     const float orr = h ? xr[k] : pr, oi = h ? xi[k] : pi;
     const float wc = T.c[k], ws = FWD ? -T.s[k] : T.s[k];
@@ -363,7 +370,7 @@ __device__ __forceinline__ void pair_dif(float (&xr)[K / 2], float (&xi)[K / 2],
   constexpr TwTable<K> T{};
 #pragma unroll
   for (int k = 0; k < H; ++k) {
-    const float pr = __shfl_xor(xr[k], 1), pi = __shfl_xor(xi[k], 1);
+    const float pr = lane_xor1(xr[k]), pi = lane_xor1(xi[k]);
     // lane 0 holds x[k], lane 1 holds x[k + H]
     const float ar = h ? pr : xr[k], ai = h ? pi : xi[k];
     const float br = h ? xr[k] : pr, bi = h ? xi[k] : pi;

@@ -196,13 +196,16 @@ def test_fullsize_forces_match_directional_derivative(forces_case):
     assert slope == pytest.approx(fn, rel=2e-3), (slope, fn)
 
 
-def test_fullsize_24k_energy_and_forces():
+def test_fullsize_24k_energy_and_forces(tmp_path):
     """The 24k box in the bench's energy + forces configuration (128 probes x 50 steps,
     forces, kept forward grids, measured shape, graph replay): per-probe quadrature
     against the golden, replay against eager, and along u = F/|F| the central difference
-    of the GPU energy equals |F| (a property that holds at any size)."""
+    of the GPU energy equals |F| (a property that holds at any size). The eager plan
+    measures its launch shape and the graph plan reads it from the same cache, so both run
+    the same summation order and must agree bit for bit."""
     import paper_2307_02278_amd as P
     wl = synth.workload("batched24k")
+    cache = str(tmp_path / "shapes.jsonl")
     s = wl.systems[0]
     ds = P.DeviceSystem(s.pos, s.cell, s.alpha, s.omega, s.rvdw)
     out = {}
@@ -210,7 +213,8 @@ def test_fullsize_24k_energy_and_forces():
         prm = P.Params(real_cutoff=wl.real_cutoff_angstrom * A, grid=(96, 96, 96),
                        n_probes=wl.n_probes, n_steps=wl.n_steps, block=wl.block,
                        precision=P.PREC_MIXED, seed=wl.probe_seed, want_forces=True,
-                       store_grids=True, tune=P.TUNE_MEASURE, graph=graph)
+                       store_grids=True, tune=P.TUNE_MEASURE, tune_cache=cache,
+                       graph=graph)
         plan = P.Plan([ds], prm)
         e, f = plan.execute(forces=True)
         e, f = plan.execute(forces=True)

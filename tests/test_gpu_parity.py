@@ -168,6 +168,25 @@ def test_matvec_mixed_noncubic_odd_half_lengths(grid, comp):
     assert _err(got, want, f"grid {grid} comp {comp}") < MIXED_TOL[comp]
 
 
+@pytest.mark.parametrize("k3", [12, 20, 36, 60, 72, 80, 96, 100, 108, 120, 128, 90])
+def test_matvec_z_convolution_lengths(k3):
+    """The z pass with the convolution (register transform over lane pairs, the lanes
+    exchanging values by quad permutations) at lengths from 12 to 128 with radices 2, 3
+    and 5: reciprocal part alone, float32 grid, 16 right-hand sides, against the oracle's
+    transform."""
+    import paper_2307_02278_amd as P
+    base = synth.tiny_random(seed=7, n=60)
+    cell = np.diag([10.0, 11.5, 13.0]) * A
+    pos = base.pos * np.array([1.0, 1.15, 1.3])
+    s = synth.System("ortho", pos, cell, base.alpha[:60], base.omega[:60], base.rvdw[:60])
+    plan, _ = _plan(s, P.PREC_MIXED, 16, grid=(16, 18, k3), tau_ang=0.35, rc_ang=13.0)
+    op = _oracle_op(s, plan)
+    v = torch.randn(16, s.n, 3, dtype=torch.float64, generator=torch.Generator().manual_seed(9))
+    got = plan.matvec(v.cuda(), components=4).cpu()
+    want = op(v.permute(1, 2, 0), 4).permute(2, 0, 1)
+    assert _err(got, want, f"K3 {k3}") < MIXED_TOL[4]
+
+
 def _compare_lanczos(s, prec, block, R, m, tol_q, tol_e, **kw):
     import paper_2307_02278_amd as P
     plan, _ = _plan(s, prec, block, R=R, m=m, **kw)
