@@ -679,7 +679,11 @@ double time_matvec(Plan& plan, System& S, int reps) {
 // Coordinate search over the shape knobs on the system's real data: the pair kernel's
 // residency together with the side stream, then its lanes per target or the matrix-core
 // kernel with its candidate split, then the gather's work-group size, then the grid
-// chunk width, then the residency once more under the chosen chunk. The fused x-line
+// chunk width, then the residency once more under the chosen chunk. Where the
+// matrix-core kernel applies it is the starting point, with its widest candidate split:
+// alone it is the faster pair kernel by about a fifth, while beside the side stream's
+// grid chain the two kernels often time within the 2 % margin, and a start from the
+// vector kernel would then keep the slower one. The fused x-line
 // spread is left out: it runs about four times slower than the tile spread plus the x
 // pass on a 96^3 grid with 24,000 atoms (each atom's loads and weights are repeated on
 // all 36 lines it touches).
@@ -688,8 +692,17 @@ void tune_system(Plan& plan, System& S, int sys_index) {
   const int B = plan.B;
   launch_probes(S.geo, S.buf, B, B, 0, plan.prm.seed, sys_index, sizeof(R) == 4, plan.stream);
   const bool list = S.buf.pg_T != nullptr && S.geo.replica_cut <= 0.0;
+  // the matrix-core launcher's rule: B / (128 or 64) column wavefronts times NK candidate
+  // shares, at most 4 wavefronts per work-group
+  const bool mfma = list && plan.prec == MBD_PREC_MIXED && B % 64 == 0 && B <= 256;
+  const int mfma_nn = B / (B % 128 == 0 ? 128 : 64);
   mbd_shape best = kBuiltinShape;
+  if (mfma) {
+    best.pair_mode = 1;
+    best.pair_subsets = mfma_nn * 4 <= 4 ? 4 : (mfma_nn * 2 <= 4 ? 2 : 1);
+  }
   apply_shape(plan, S, best);
+  best = S.shape;
   double tbest = time_matvec<R>(plan, S, 5);
   // a candidate replaces the best shape only when it is at least 2 % faster (fastest of
   // five timings each), so that timing noise does not pick residency caps or other
@@ -719,19 +732,18 @@ void tune_system(Plan& plan, System& S, int sys_index) {
     for (int ns : {1, 2, 4}) {
       if (ns * B < 64) continue;
       mbd_shape sh = base;
+      sh.pair_mode = 0;
       sh.pair_subsets = ns;
-      trial(sh);
+      if (base.pair_mode != 0 || base.pair_subsets != ns) trial(sh);
     }
-    // the matrix-core kernel with 4, 2 or 1 wavefronts per group's candidates (the widest
-    // split first: it is the fastest alone, and beside the grid stages the three are
-    // usually within the 2 % margin)
-    if (plan.prec == MBD_PREC_MIXED && B % 64 == 0 && B <= 256)
+    // the matrix-core kernel with 4, 2 or 1 wavefronts per group's candidates
+    if (mfma)
       for (int nk : {4, 2, 1}) {
-        if ((B / 64) * nk > 4) continue;
+        if (mfma_nn * nk > 4) continue;
         mbd_shape sh = base;
         sh.pair_mode = 1;
         sh.pair_subsets = nk;
-        trial(sh);
+        if (base.pair_mode != 1 || base.pair_subsets != nk) trial(sh);
       }
   }
   {
