@@ -175,6 +175,7 @@ void allocate_system(Plan& plan, System& S, int R_probes, int m) {
     b.line_atoms = dalloc<int>(plan, (size_t)g.p * g.p * n, by);
   }
   b.G = dalloc<R>(plan, (size_t)g.K[2] * g.K[1] * (g.K[0] / 2 + 1), by);
+  b.Gt = dalloc<R>(plan, (size_t)g.K[2] * g.K[1] * (g.K[0] / 2 + 1), by);
   b.tw = dalloc<R>(plan, 2 * (size_t)(g.K[0] + g.K[1] + g.K[2]), by);
   const size_t vec = 3 * (size_t)n * B;
   b.W = dalloc<double>(plan, vec * m, by);
@@ -226,6 +227,15 @@ void allocate_system(Plan& plan, System& S, int R_probes, int m) {
   std::vector<R> G, tw;
   host_tables<R>(g, G, tw);
   check(hipMemcpy(b.G, G.data(), G.size() * sizeof(R), hipMemcpyHostToDevice), "copy G");
+  {
+    // the same values with kz innermost: one z line of G per (ky, kx), contiguous
+    const size_t K2 = g.K[1], K3 = g.K[2], KX = g.K[0] / 2 + 1;
+    std::vector<R> Gt(G.size());
+    for (size_t z = 0; z < K3; ++z)
+      for (size_t yx = 0; yx < K2 * KX; ++yx) Gt[yx * K3 + z] = G[z * K2 * KX + yx];
+    check(hipMemcpy(b.Gt, Gt.data(), Gt.size() * sizeof(R), hipMemcpyHostToDevice),
+          "copy Gt");
+  }
   check(hipMemcpy(b.tw, tw.data(), tw.size() * sizeof(R), hipMemcpyHostToDevice), "copy tw");
 }
 

@@ -130,6 +130,7 @@ struct SysBuffers {
   int* line_start = nullptr;   // [K2 K3 + 1]
   int* line_atoms = nullptr;   // [p^2 n]
   void* G = nullptr;           // Real [K3][K2][K1/2 + 1]
+  void* Gt = nullptr;          // Real [K2][K1/2 + 1][K3]: G with kz innermost (register z pass)
   void* tw = nullptr;          // Real [2][K1 + K2 + K3] twiddles exp(-2 pi i j / K_a)
   int* images = nullptr;       // [n_images][3] integer lattice vectors (replica method)
   // direct-space tensor list (B >= 16): groups of kGroup sorted targets

@@ -391,6 +391,25 @@ __device__ __forceinline__ float& at(float* base, uint32_t e) {
   return *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + (e << 2));
 }
 
+// The same grid addressed through a buffer resource built from the wave-uniform base:
+// a load or store takes a per-lane byte offset (one vector register shared by a whole
+// line) plus a wave-uniform byte offset in a scalar register, so that a line of K
+// elements holds one vector register of addresses instead of one per element. The
+// range is left unbounded (4 GiB), since the offsets are those of at() above.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t wave_rsrc(float* base) {
+  // word 3: 32-bit data format, the untyped-load setting for this architecture family
+  return __builtin_amdgcn_make_buffer_rsrc(base, 0, -1, 0x00020000);
+}
+__device__ __forceinline__ float ld_line(__amdgpu_buffer_rsrc_t r, uint32_t vbyte,
+                                         uint32_t sbyte) {
+  // the builtin moves 32-bit integers: reinterpret the bits, never convert the value
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vbyte, sbyte, 0));
+}
+__device__ __forceinline__ void st_line(__amdgpu_buffer_rsrc_t r, float v, uint32_t vbyte,
+                                        uint32_t sbyte) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, vbyte, sbyte, 0);
+}
+
 template <int K, int MODE>
 __global__ void __launch_bounds__(64)
 k_fft_reg(float* __restrict__ grid, GridDims gd, const float* __restrict__ G) {
@@ -446,35 +465,46 @@ k_fft_reg(float* __restrict__ grid, GridDims gd, const float* __restrict__ G) {
       xi[m] = n <= H ? vi : -vi;
     }
   } else {
+    // lane h reads x[2m + h]: lane part h stride (imaginary rows BG further), uniform
+    // part 2m stride
+    const __amdgpu_buffer_rsrc_t rs = wave_rsrc(gw);
+    const uint32_t vb = (lo + (uint32_t)h * stride) << 2;
+    const uint32_t vbi = vb + ((uint32_t)BG << 2);
 #pragma unroll
     for (int m = 0; m < H; ++m) {
-      const uint32_t o = lo + (uint32_t)(2 * m + h) * stride;
-      xr[m] = at(gw, o);
-      xi[m] = at(gw, o + BG);
+      const uint32_t sb = ((uint32_t)(2 * m) * stride) << 2;
+      xr[m] = ld_line(rs, vb, sb);
+      xi[m] = ld_line(rs, vbi, sb);
     }
   }
   constexpr bool FWD = (MODE == kXFwd || MODE == kYFwd || MODE == kZConv);
   reg_stages<H, 0, FWD>(xr, xi);
   pair_dit<K, FWD>(xr, xi, h);
   if (MODE == kZConv) {
-    // natural halves: lane h holds X[h H + k]
-    // G is [K3][K2][KX]: a 32-bit offset from the kernel-argument base per element
-    const uint32_t goff = (uint32_t)line;  // y * KX + kx
-    const uint32_t gstride = (uint32_t)gd.K2 * gd.KX;
+    // natural halves: lane h holds X[h H + k]. G here is the kz-innermost copy
+    // [K2][KX][K3], so the lane's H factors are one run: one address and immediate
+    // offsets for all H loads.
+    const float* gl = G + (size_t)line * K + h * H;
 #pragma unroll
     for (int k = 0; k < H; ++k) {
-      const float w = G[goff + (uint32_t)(h * H + k) * gstride];
+      const float w = gl[k];
       xr[k] *= w;
       xi[k] *= w;
+      // the product is formed here: folded into the exchange step below, it kept the
+      // factor, the plain value and the product live together
+      asm("" : "+v"(xr[k]), "+v"(xi[k]));
     }
     pair_dif<K, false>(xr, xi, h);
     reg_stages<H, 0, false>(xr, xi);
     // decimated output: lane h holds x[2k + h]
+    const __amdgpu_buffer_rsrc_t rs = wave_rsrc(gw);
+    const uint32_t vb = (lo + (uint32_t)h * stride) << 2;
+    const uint32_t vbi = vb + ((uint32_t)BG << 2);
 #pragma unroll
     for (int k = 0; k < H; ++k) {
-      const uint32_t o = lo + (uint32_t)(2 * k + h) * stride;
-      at(gw, o) = xr[k];
-      at(gw, o + BG) = xi[k];
+      const uint32_t sb = ((uint32_t)(2 * k) * stride) << 2;
+      st_line(rs, xr[k], vb, sb);
+      st_line(rs, xi[k], vbi, sb);
     }
     return;
   }
@@ -493,11 +523,15 @@ k_fft_reg(float* __restrict__ grid, GridDims gd, const float* __restrict__ G) {
 #pragma unroll
     for (int k = 0; k < H; ++k) at(gw, lo + (uint32_t)(h * H + k) * stride) = xr[k];
   } else {
+    // lane h writes X[h H + k]: lane part h H stride, uniform part k stride
+    const __amdgpu_buffer_rsrc_t rs = wave_rsrc(gw);
+    const uint32_t vb = (lo + (uint32_t)(h * H) * stride) << 2;
+    const uint32_t vbi = vb + ((uint32_t)BG << 2);
 #pragma unroll
     for (int k = 0; k < H; ++k) {
-      const uint32_t o = lo + (uint32_t)(h * H + k) * stride;
-      at(gw, o) = xr[k];
-      at(gw, o + BG) = xi[k];
+      const uint32_t sb = ((uint32_t)k * stride) << 2;
+      st_line(rs, xr[k], vb, sb);
+      st_line(rs, xi[k], vbi, sb);
     }
   }
 }
@@ -732,7 +766,7 @@ template <> struct FftShape<double> { static constexpr int NC = 32, P = 8; };
 
 template <typename R, int MODE>
 void launch_pass(int K, R* grid, const GridDims& gd, int nchunks, const R* twc, const R* tws,
-                 const R* G, hipStream_t st) {
+                 const R* G, const R* Gt, hipStream_t st) {
   constexpr int NC = FftShape<R>::NC, P = FftShape<R>::P;
   long nlines;
   if (MODE == kXFwd || MODE == kXInv) nlines = (long)gd.K2 * gd.K3;
@@ -758,7 +792,7 @@ void launch_pass(int K, R* grid, const GridDims& gd, int nchunks, const R* twc, 
       switch (K) {
 #define MBD_REG(KK)                                                                    \
         case KK:                                                                       \
-          k_fft_reg<KK, MODE><<<g2, 64, 0, st>>>((float*)grid, gd, (const float*)G);   \
+          k_fft_reg<KK, MODE><<<g2, 64, 0, st>>>((float*)grid, gd, (const float*)Gt);   \
           return;
         MBD_REG_SIZES(MBD_REG)
 #undef MBD_REG
@@ -815,12 +849,13 @@ void launch_fft_pass(const Geometry& geo, const SysBuffers& b, int B, int BG, in
   const R* c1 = tw + geo.K[0];
   const R* c2 = tw + geo.K[0] + geo.K[1];
   const R* G = (const R*)b.G;
+  const R* Gt = (const R*)b.Gt;
   switch (pass) {
-    case 0: launch_pass<R, kXFwd>(geo.K[0], grid, gd, nchunks, c0, c0 + Ksum, G, st); break;
-    case 1: launch_pass<R, kYFwd>(geo.K[1], grid, gd, nchunks, c1, c1 + Ksum, G, st); break;
-    case 2: launch_pass<R, kZConv>(geo.K[2], grid, gd, nchunks, c2, c2 + Ksum, G, st); break;
-    case 3: launch_pass<R, kYInv>(geo.K[1], grid, gd, nchunks, c1, c1 + Ksum, G, st); break;
-    default: launch_pass<R, kXInv>(geo.K[0], grid, gd, nchunks, c0, c0 + Ksum, G, st); break;
+    case 0: launch_pass<R, kXFwd>(geo.K[0], grid, gd, nchunks, c0, c0 + Ksum, G, Gt, st); break;
+    case 1: launch_pass<R, kYFwd>(geo.K[1], grid, gd, nchunks, c1, c1 + Ksum, G, Gt, st); break;
+    case 2: launch_pass<R, kZConv>(geo.K[2], grid, gd, nchunks, c2, c2 + Ksum, G, Gt, st); break;
+    case 3: launch_pass<R, kYInv>(geo.K[1], grid, gd, nchunks, c1, c1 + Ksum, G, Gt, st); break;
+    default: launch_pass<R, kXInv>(geo.K[0], grid, gd, nchunks, c0, c0 + Ksum, G, Gt, st); break;
   }
 }
 
