@@ -48,12 +48,10 @@ k_spread(const Geometry geo, const int* __restrict__ tile_start,
   constexpr int NWT = 6 * T;            // staged weights per atom: w, dw along x, y, z
   __shared__ R wts_all[4][64][NWT];
   __shared__ int sat_all[4][64];        // atom index of each staged slot
-  __shared__ int smk_all[4][64];        // its tile rows: bit T + q (y), 2 T + q (z)
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int lane = threadIdx.x & 63;
   R(*wts)[NWT] = wts_all[wave];
   int* sat = sat_all[wave];
-  int* smk = smk_all[wave];
   const int ntiles = geo.tiles[0] * geo.tiles[1] * geo.tiles[2];
   // Blocks are dealt round-robin to the 8 XCDs (gridDim.x is a multiple of 8):
   // each XCD takes one contiguous range of tiles, a slab of the grid, so the
@@ -88,7 +86,6 @@ k_spread(const Geometry geo, const int* __restrict__ tile_start,
       if (o[2] < 0) o[2] += K3;
       const R* thp = th + (size_t)s * 3 * P;
       const R* dthp = dth + (size_t)s * 3 * P;
-      int mk = 0;
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
@@ -97,10 +94,8 @@ k_spread(const Geometry geo, const int* __restrict__ tile_start,
           const bool v = t >= 0 && t < P;
           wts[lane][(2 * ax) * T + q] = v ? thp[ax * P + t] : R(0);
           wts[lane][(2 * ax + 1) * T + q] = v ? dthp[ax * P + t] : R(0);
-          mk |= v ? 1 << (ax * T + q) : 0;
         }
       sat[lane] = s;
-      smk[lane] = mk;
     }
     // the batch's LDS writes are visible to the whole wavefront before it reads them
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -133,17 +128,12 @@ k_spread(const Geometry geo, const int* __restrict__ tile_start,
         wz[q] = wa[4 * T + q]; dwz[q] = wa[5 * T + q];
       }
       if (NSUB == 1) {
-        // the tile rows (py, pz) inside the stencil, each over all T points in x: the
-        // staged x weights are zero outside it, and a branch-free row issues fewer
-        // instructions than uniform per-point tests. The row test is uniform (a scalar
-        // branch); a skipped row would only have added zeros.
-        const int mk = __builtin_amdgcn_readfirstlane(smk[a]);
+        // every point of the tile: the staged weights are zero outside the stencil, and
+        // a branch-free loop issues fewer instructions than uniform per-point tests
 #pragma unroll
         for (int pz = 0; pz < T; ++pz) {
-          if (!(mk & (1 << (2 * T + pz)))) continue;
 #pragma unroll
           for (int py = 0; py < T; ++py) {
-            if (!(mk & (1 << (T + py)))) continue;
             const R A = d0 * wy[py] * wz[pz];
             const R Bc = d1 * dwy[py] * wz[pz] + d2 * wy[py] * dwz[pz];
 #pragma unroll
