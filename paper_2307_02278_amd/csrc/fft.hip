@@ -579,14 +579,21 @@ k_fft_x_real(float* __restrict__ grid, GridDims gd) {
     at(gw, lo_st + stride) = 0.f;
     at(gw, lo_st + (uint32_t)(2 * M) * stride) = zr[0] - zi[0];
     at(gw, lo_st + (uint32_t)(2 * M + 1) * stride) = 0.f;
+    // bins k and M - k read the same two points, so they are formed together and both
+    // points die at once (in plain k order every point stayed live until its mirror bin)
 #pragma unroll
-    for (int k = 1; k < M; ++k) {
-      const float fer = 0.5f * (zr[k] + zr[M - k]), fei = 0.5f * (zi[k] - zi[M - k]);
-      const float forr = 0.5f * (zi[k] + zi[M - k]), foi = -0.5f * (zr[k] - zr[M - k]);
-      // W_K^k = cos - i sin
-      const float wr = T.c[k] * forr + T.s[k] * foi, wi = T.c[k] * foi - T.s[k] * forr;
-      at(gw, lo_st + (uint32_t)(2 * k) * stride) = fer + wr;
-      at(gw, lo_st + (uint32_t)(2 * k + 1) * stride) = fei + wi;
+    for (int k = 1; k <= M / 2; ++k) {
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int j = e ? M - k : k;
+        if (e && j == k) break;
+        const float fer = 0.5f * (zr[j] + zr[M - j]), fei = 0.5f * (zi[j] - zi[M - j]);
+        const float forr = 0.5f * (zi[j] + zi[M - j]), foi = -0.5f * (zr[j] - zr[M - j]);
+        // W_K^j = cos - i sin
+        const float wr = T.c[j] * forr + T.s[j] * foi, wi = T.c[j] * foi - T.s[j] * forr;
+        at(gw, lo_st + (uint32_t)(2 * j) * stride) = fer + wr;
+        at(gw, lo_st + (uint32_t)(2 * j + 1) * stride) = fei + wi;
+      }
     }
   } else {
     // zr, zi hold X[0..M); X[M] is the last complex pair of the half spectrum
