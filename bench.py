@@ -57,13 +57,14 @@ def pair_kernel_name(shape, B, n_atoms):
     for B right-hand sides (the launcher's rules in pair.hip)."""
     ngroups = (n_atoms + 15) // 16
     ns_given = shape.get("pair_subsets", 0)
-    if shape.get("pair_mode", 0) == 1 and B % 64 == 0 and B <= 256:
-        wide = 128 if B % 128 == 0 else 64
+    mode = shape.get("pair_mode", 0)
+    if mode in (1, 2) and B % 64 == 0 and B <= 256:
+        wide = 128 if (mode == 1 and B % 128 == 0) else 64
         nn, nk = B // wide, ns_given or 1
         while nk > 1 and nn * nk > 4:
             nk //= 2
         nt = 8 if wide == 128 else 4
-        nn_t = 2 if (nk == 2 and wide == 128 and nn == 2) else 1
+        nn_t = 2 if (nk == 2 and nn == 2) else 1
         return f"k_pair_mfma<{nk}, {nt}, {nn_t}>"
     ns = 1 if B >= 64 else 64 // B
     if ns_given > 0:

@@ -110,8 +110,12 @@ typedef struct {
                              right-hand side, skipping out-of-range pairs; 1 => matrix
                              cores (v_mfma_f32_16x16x4_f32) over the dense per-group
                              product (mixed precision, block a multiple of 64 up to 256;
-                             otherwise 0 is used). With forces, 1 also computes the
-                             direct force term on the matrix cores when block <= 128     */
+                             otherwise 0 is used), a wavefront holding 128 right-hand
+                             sides where block is a multiple of 128, else 64; 2 => the
+                             same with 64 right-hand sides per wavefront (half the
+                             accumulator registers). With forces, 1 and 2 also compute
+                             the direct force term on the matrix cores when
+                             block <= 128                                                 */
 } mbd_shape;
 
 enum {

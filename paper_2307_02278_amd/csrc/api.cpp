@@ -569,7 +569,7 @@ bool valid_shape(const mbd_shape& sh, int B) {
          pow2chunk && sh.overlap >= 0 && sh.overlap <= 2 &&
          (sh.gather_waves == 0 || sh.gather_waves == 4 || sh.gather_waves == 8) &&
          (sh.spread_mode == 0 || sh.spread_mode == 1) &&
-         (sh.pair_mode == 0 || sh.pair_mode == 1);
+         (sh.pair_mode >= 0 && sh.pair_mode <= 2);
 }
 
 void apply_shape(const Plan& plan, System& S, const mbd_shape& sh) {
@@ -746,8 +746,10 @@ void tune_system(Plan& plan, System& S, int sys_index) {
       sh.pair_subsets = ns;
       if (base.pair_mode != 0 || base.pair_subsets != ns) trial(sh);
     }
-    // the matrix-core kernel with 4, 2 or 1 wavefronts per group's candidates
-    if (mfma)
+    // the matrix-core kernel with 4, 2 or 1 wavefronts per group's candidates, and, where
+    // B is a multiple of 128, with 64-column wavefronts (fewer accumulator registers per
+    // wavefront, which leaves room for the transforms beside it)
+    if (mfma) {
       for (int nk : {4, 2, 1}) {
         if (mfma_nn * nk > 4) continue;
         mbd_shape sh = base;
@@ -755,6 +757,15 @@ void tune_system(Plan& plan, System& S, int sys_index) {
         sh.pair_subsets = nk;
         if (base.pair_mode != 1 || base.pair_subsets != nk) trial(sh);
       }
+      if (B % 128 == 0)
+        for (int nk : {2, 1}) {
+          if ((B / 64) * nk > 4) continue;
+          mbd_shape sh = base;
+          sh.pair_mode = 2;
+          sh.pair_subsets = nk;
+          trial(sh);
+        }
+    }
   }
   {
     mbd_shape sh = best;
@@ -912,7 +923,7 @@ mbd_status mbd_plan_create(mbd_plan* out, const mbd_system* systems, int32_t n_s
   if (prm.tune == MBD_TUNE_GIVEN && !valid_shape(prm.shape, prm.block))
     return fail(MBD_E_ARG, "shape: pair_wg_per_cu in [0, 64], pair_subsets 0/1/2/4, grid_chunk "
                            "0 or a power of two <= 64 dividing block, overlap 0/1/2, "
-                           "gather_waves 0/4/8, spread_mode 0/1, pair_mode 0/1");
+                           "gather_waves 0/4/8, spread_mode 0/1, pair_mode 0/1/2");
 
   const int BG_plan = std::min(prm.block, prm.precision == MBD_PREC_FP64 ? 16 : 64);
   std::vector<Geometry> geos(n_sys);

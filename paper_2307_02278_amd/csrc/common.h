@@ -51,7 +51,8 @@ struct Geometry {
   int pair_blocks;       // work-groups of a launch; 0 => one per 16-atom group
   int pair_ns;           // target subsets per wavefront (1, 2, 4); 0 => size rule
   int gather_waves;      // wavefronts per work-group of the gather-type kernels (4 or 8)
-  int pair_mode;         // 0 => vector list kernel; 1 => matrix-core list kernel (float)
+  int pair_mode;         // 0 => vector list kernel; 1 => matrix-core list kernel (float);
+                         // 2 => the same with 64-column wavefronts
   int line_lists;        // 1 => the setup also builds the x-line atom lists (fused spread)
 };
 

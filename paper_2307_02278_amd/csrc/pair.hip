@@ -1015,11 +1015,11 @@ void launch_pair(const Geometry& g, const SysBuffers& b, int B, hipStream_t st) 
   const int2* H = b.pg_hdr;
   const R* T = (const R*)b.pg_T;
   if constexpr (sizeof(R) == 4) {
-    // matrix cores: 128 right-hand sides per wavefront (64 when B = 64 or 192), B / 128
-    // column wavefronts x NK candidate shares per group (NK from pair_ns, at most 4
-    // wavefronts per work-group)
-    if (g.pair_mode == 1 && B % 64 == 0 && B <= 256) {
-      const int wide = B % 128 == 0 ? 128 : 64;
+    // matrix cores: 128 right-hand sides per wavefront (64 when B = 64 or 192, or with
+    // pair_mode 2), B / wide column wavefronts x NK candidate shares per group (NK from
+    // pair_ns, at most 4 wavefronts per work-group)
+    if ((g.pair_mode == 1 || g.pair_mode == 2) && B % 64 == 0 && B <= 256) {
+      const int wide = (g.pair_mode == 1 && B % 128 == 0) ? 128 : 64;
       const int nn = B / wide;
       int nk = g.pair_ns > 0 ? g.pair_ns : 1;
       while (nk > 1 && nn * nk > 4) nk /= 2;
@@ -1036,7 +1036,7 @@ void launch_pair(const Geometry& g, const SysBuffers& b, int B, hipStream_t st) 
       } else if (wide == 128) {
         if (nk == 4) MBD_PM(4, 8, 1); else if (nn == 1) MBD_PM(2, 8, 1); else MBD_PM(2, 8, 2);
       } else {
-        if (nk == 4) MBD_PM(4, 4, 1); else MBD_PM(2, 4, 1);
+        if (nk == 4) MBD_PM(4, 4, 1); else if (nn == 1) MBD_PM(2, 4, 1); else MBD_PM(2, 4, 2);
       }
 #undef MBD_PM
       return;
@@ -1081,7 +1081,7 @@ void launch_pair_force(const Geometry& g, const SysBuffers& b, int B, hipStream_
   const R* q = (const R*)b.dq;
   if constexpr (sizeof(R) == 4) {
     // matrix cores, with the matrix-core direct sum: four wavefronts per group
-    if (g.pair_mode == 1 && B % 16 == 0 && B <= 128) {
+    if ((g.pair_mode == 1 || g.pair_mode == 2) && B % 16 == 0 && B <= 128) {
       k_pair_force_mfma<4><<<pair_blocks(g, ngroups), 256, 0, st>>>(
           g, H, (const float*)F, b.pg_count, b.pg_cap, (const float*)p, (const float*)q,
           b.fsum + 3 * (size_t)g.n, B);

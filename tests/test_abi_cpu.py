@@ -115,7 +115,7 @@ def _create(s, p, nsys=1):
     (lambda s, p: (setattr(p, "tune", 2), setattr(p.shape, "pair_wg_per_cu", -1)), L.MBD_E_ARG),
     (lambda s, p: (setattr(p, "tune", 2), setattr(p.shape, "gather_waves", 6)), L.MBD_E_ARG),
     (lambda s, p: (setattr(p, "tune", 2), setattr(p.shape, "spread_mode", 2)), L.MBD_E_ARG),
-    (lambda s, p: (setattr(p, "tune", 2), setattr(p.shape, "pair_mode", 2)), L.MBD_E_ARG),
+    (lambda s, p: (setattr(p, "tune", 2), setattr(p.shape, "pair_mode", 3)), L.MBD_E_ARG),
 ])
 def test_invalid_arguments_fail_before_device_work(mutate, code):
     s, p = _args()

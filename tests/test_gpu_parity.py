@@ -392,36 +392,38 @@ def water600():
     return synth.water_box(200, seed=11)
 
 
-@pytest.mark.parametrize("block,nk", [(64, 1), (64, 2), (64, 4), (128, 1), (128, 2), (128, 4), (256, 1),
-                                      (256, 2)])
-def test_matvec_matrix_core_pair_kernel(water600, block, nk):
+@pytest.mark.parametrize("block,nk,mcore", [(64, 1, 1), (64, 2, 1), (64, 4, 1), (128, 1, 1),
+                                            (128, 2, 1), (128, 4, 1), (256, 1, 1), (256, 2, 1),
+                                            (128, 1, 2), (128, 2, 2), (256, 1, 2)])
+def test_matvec_matrix_core_pair_kernel(water600, block, nk, mcore):
     """The direct-space sum on the matrix cores (dense per-group product over 16 targets
     x 3 components, 600 atoms: 38 groups, the last one ragged, and candidate lists whose
-    3 x count is not a multiple of the 4 rows per instruction), against the oracle
-    element by element and against the vector list kernel to float32 rounding."""
+    3 x count is not a multiple of the 4 rows per instruction), with 128- or 64-column
+    wavefronts (pair_mode 1 or 2), against the oracle element by element and against the
+    vector list kernel to float32 rounding."""
     import paper_2307_02278_amd as P
     s = water600
     ds = P.DeviceSystem(s.pos, s.cell, s.alpha, s.omega, s.rvdw)
     v = torch.randn(block, s.n, 3, dtype=torch.float64,
                     generator=torch.Generator().manual_seed(17))
     got = {}
-    for mode in (0, 1):
+    for mode in (0, mcore):
         prm = P.Params(real_cutoff=7.0 * A, grid=(24, 24, 24), n_probes=block, n_steps=4,
                        block=block, precision=P.PREC_MIXED, tune=P.TUNE_GIVEN,
                        shape=dict(overlap=1, pair_mode=mode, pair_subsets=nk if mode else 0))
         plan = P.Plan([ds], prm)
         assert plan.info(0).shape.pair_mode == mode
         got[mode] = {c: plan.matvec(v.cuda(), components=c).cpu() for c in (2, 15)}
-        if mode == 1:
+        if mode:
             op = _oracle_op(s, plan)
             for c in (2, 15):
                 want = op(v.permute(1, 2, 0), c).permute(2, 0, 1)
-                assert _err(got[1][c], want, f"matrix cores B={block} NK={nk} comp {c}") \
-                    < MIXED_TOL[c]
+                assert _err(got[mode][c], want,
+                            f"matrix cores mode {mode} B={block} NK={nk} comp {c}") < MIXED_TOL[c]
         plan.check()
         plan.close()
     # two float32 summation orders of the same terms (the same bits when NK = 1)
-    d = _err(got[1][2], got[0][2], "matrix cores vs vector kernel")
+    d = _err(got[mcore][2], got[0][2], "matrix cores vs vector kernel")
     assert d < MIXED_TOL[2]
 
 

@@ -48,7 +48,9 @@ SHAPES = [dict(pair_wg_per_cu=0, pair_subsets=0, grid_chunk=0, overlap=1),
           dict(pair_wg_per_cu=3, pair_subsets=1, grid_chunk=0, overlap=0, spread_mode=1),
           dict(pair_wg_per_cu=0, pair_subsets=1, grid_chunk=0, overlap=1, pair_mode=1),
           dict(pair_wg_per_cu=2, pair_subsets=1, grid_chunk=0, overlap=2, pair_mode=1),
-          dict(pair_wg_per_cu=0, pair_subsets=2, grid_chunk=0, overlap=1, pair_mode=1)]
+          dict(pair_wg_per_cu=0, pair_subsets=2, grid_chunk=0, overlap=1, pair_mode=1),
+          dict(pair_wg_per_cu=0, pair_subsets=1, grid_chunk=0, overlap=2, pair_mode=2),
+          dict(pair_wg_per_cu=2, pair_subsets=2, grid_chunk=0, overlap=1, pair_mode=2)]
 
 
 def test_shapes_give_the_same_bits_and_match_the_oracle(water600):
