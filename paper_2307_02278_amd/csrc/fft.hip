@@ -410,9 +410,11 @@ __device__ __forceinline__ void st_line(__amdgpu_buffer_rsrc_t r, float v, uint3
   __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, vbyte, sbyte, 0);
 }
 
+// Gz (the z pass with the convolution only): the influence function with kz innermost,
+// [K2][K1/2 + 1][K3].
 template <int K, int MODE>
 __global__ void __launch_bounds__(64)
-k_fft_reg(float* __restrict__ grid, GridDims gd, const float* __restrict__ G) {
+k_fft_reg(float* __restrict__ grid, GridDims gd, const float* __restrict__ Gz) {
   constexpr int H = K / 2;
   float* g = grid + (size_t)(blockIdx.y + gd.chunk0) * gd.chunk_elems;
   const int h = threadIdx.x & 1;
@@ -481,10 +483,9 @@ k_fft_reg(float* __restrict__ grid, GridDims gd, const float* __restrict__ G) {
   reg_stages<H, 0, FWD>(xr, xi);
   pair_dit<K, FWD>(xr, xi, h);
   if (MODE == kZConv) {
-    // natural halves: lane h holds X[h H + k]. G here is the kz-innermost copy
-    // [K2][KX][K3], so the lane's H factors are one run: one address and immediate
-    // offsets for all H loads.
-    const float* gl = G + (size_t)line * K + h * H;
+    // natural halves: lane h holds X[h H + k]. With kz innermost the lane's H factors
+    // are one run: one address and immediate offsets for all H loads.
+    const float* gl = Gz + (size_t)line * K + h * H;
 #pragma unroll
     for (int k = 0; k < H; ++k) {
       const float w = gl[k];
