@@ -1082,7 +1082,8 @@ void launch_pair_force(const Geometry& g, const SysBuffers& b, int B, hipStream_
   if constexpr (sizeof(R) == 4) {
     // matrix cores, with the matrix-core direct sum: four wavefronts per group
     if ((g.pair_mode == 1 || g.pair_mode == 2) && B % 16 == 0 && B <= 128) {
-      k_pair_force_mfma<4><<<pair_blocks(g, ngroups), 256, 0, st>>>(
+      // one work-group per group, whatever residency cap the direct sum runs with
+      k_pair_force_mfma<4><<<(ngroups + 7) / 8 * 8, 256, 0, st>>>(
           g, H, (const float*)F, b.pg_count, b.pg_cap, (const float*)p, (const float*)q,
           b.fsum + 3 * (size_t)g.n, B);
       return;
